@@ -1,0 +1,805 @@
+// Sparse-format oracle (test infrastructure only).
+//
+// A plain, slow CPU implementation of what the hybrid-format path computes, used to check
+// the GPU library. It shares no code, header, table or helper with the GPU library. Only
+// the tests, the smoke check and the benchmark's CPU-baseline leg may load it.
+//
+// What it computes, in the paper's terms ("Bring Your Own Formats and Kernels", SABLE):
+//   * the plan semantics of Sec. 3: extractors run in list order on the residual matrix,
+//     each claims the nonzeros that fit its structure into a format object, the final CSR
+//     extractor claims the rest (Sec. 3 "Extract"/"Dispatch", App. A.1);
+//   * the band extractor (Sec. 4.2, Alg. 3 ExtractBands and Alg. 4 GrowSegments) producing
+//     the VDIA format of Sec. 4.2.1 (Fig. "vdia");
+//   * the block extractor (Sec. 4.1, Alg. 1 Partition/Decompose, Alg. 2 FindBlock) producing
+//     VBR blocks (App. B, Fig. "vbr"), and a tiled delta-dense block detection used where the
+//     literal search does not scale (not in the paper; documented reading);
+//   * y = A x and Y = A X in FP64 over A's entries in row-major order (Sec. 5 "Kernels").
+//
+// Readings where the paper gives no value or rule (each is also listed in the design notes):
+//   density tests are exact integer tests with per-mille thresholds p: 1000*nnz >= p*area;
+//   d_max = all offsets; count threshold = l_seg; ribbon half-width cap W_max;
+//   candidates ordered by count descending then offset ascending; FitRibbon greedy rule;
+//   row-exclusive band mask; FindBlock ties keep the first in (o0, o1, i1) order and CSR
+//   wins ties against CSC; Trim removes the best edge (top<bottom<left<right on ties) while
+//   density strictly improves; coverage cutoff and nnz(A) refer to the VBR input residual.
+//
+// Parity pins: the worked examples of Fig. "vdia" and Fig. "vbr", closed-form block and
+// segment cases, brute-force dense products and exact-cover invariants (tests/).
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <utility>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+typedef int64_t i64;
+typedef unsigned __int128 u128;
+
+struct Thr {  // layout mirrored by the ctypes structure in oracle/__init__.py
+  int32_t delta_band_pm, delta_block_pm;
+  int64_t amin_band, amin_block;
+  int32_t lseg, wmax, dmax, coverage_pm, tile_set_mask, pad;
+};
+
+// Residual matrix: CSR with, for every stored entry, its index in the input matrix A.
+struct Mat {
+  i64 nrows = 0, ncols = 0;
+  std::vector<i64> ptr;
+  std::vector<int32_t> col;
+  std::vector<float> val;
+  std::vector<i64> id;
+  i64 nnz() const { return (i64)col.size(); }
+};
+
+// Column-major companion of a residual (for the CSC pass of Alg. 1/2 and column counts).
+struct Csc {
+  std::vector<i64> ptr;
+  std::vector<int32_t> row;
+};
+
+struct Seg { i64 i0, j, L, U, z, d; };     // rows [i0, j), offsets [d-L, d+U]
+struct Blk { i64 r0, r1, c0, c1; };        // rows [r0, r1), columns [c0, c1)
+
+template <class T>
+void put(T* dst, const std::vector<T>& v) {
+  if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(T));
+}
+
+struct Plan {
+  // VDIA (Sec. 4.2.1): val diagonal-major per segment, idiag per segment, seg_* metadata
+  std::vector<float> vdia_val;
+  std::vector<int32_t> idiag, seg_row_start, seg_nrows, seg_ndiags, seg_idiag_ptr;
+  std::vector<i64> seg_val_ptr;
+  // VBR (App. B): blocks (r0, r1, c0, c1) sorted by (r0, c0), values column-major per block
+  std::vector<int32_t> blk;
+  std::vector<i64> blk_val_ptr;
+  std::vector<float> vbr_val;
+  int32_t vbr_tile = 0, vbr_mode_used = 0;
+  // CSR remainder
+  std::vector<i64> csr_ptr;
+  std::vector<int32_t> csr_col;
+  std::vector<float> csr_val;
+  // owner of every input entry: 0 VDIA, 1 VBR, 2 CSR; slot = index into that format's values
+  std::vector<int8_t> owner;
+  std::vector<i64> slot;
+  i64 nrows = 0, ncols = 0;
+};
+
+// ---------------------------------------------------------------------------------------
+// Residual helpers
+
+// Number of entries of row i with column in [clo, chi].
+i64 row_count(const Mat& R, i64 i, i64 clo, i64 chi) {
+  if (clo < 0) clo = 0;
+  if (chi > R.ncols - 1) chi = R.ncols - 1;
+  if (clo > chi) return 0;
+  const int32_t* b = R.col.data() + R.ptr[i];
+  const int32_t* e = R.col.data() + R.ptr[i + 1];
+  return (i64)(std::upper_bound(b, e, (int32_t)chi) - std::lower_bound(b, e, (int32_t)clo));
+}
+
+bool present(const Mat& R, i64 i, i64 c) {
+  if (c < 0 || c >= R.ncols) return false;
+  return row_count(R, i, c, c) > 0;
+}
+
+// Number of entries of column c with row in [rlo, rhi].
+i64 col_count(const Mat& R, const Csc& C, i64 c, i64 rlo, i64 rhi) {
+  if (rlo < 0) rlo = 0;
+  if (rhi > R.nrows - 1) rhi = R.nrows - 1;
+  if (rlo > rhi) return 0;
+  const int32_t* b = C.row.data() + C.ptr[c];
+  const int32_t* e = C.row.data() + C.ptr[c + 1];
+  return (i64)(std::upper_bound(b, e, (int32_t)rhi) - std::lower_bound(b, e, (int32_t)rlo));
+}
+
+Csc transpose(const Mat& R) {
+  Csc C;
+  C.ptr.assign(R.ncols + 1, 0);
+  for (i64 k = 0; k < R.nnz(); ++k) C.ptr[R.col[k] + 1]++;
+  for (i64 c = 0; c < R.ncols; ++c) C.ptr[c + 1] += C.ptr[c];
+  C.row.resize(R.nnz());
+  std::vector<i64> fill(C.ptr.begin(), C.ptr.end() - 1);
+  for (i64 i = 0; i < R.nrows; ++i)
+    for (i64 k = R.ptr[i]; k < R.ptr[i + 1]; ++k) C.row[fill[R.col[k]]++] = (int32_t)i;
+  return C;
+}
+
+i64 rect_nnz(const Mat& R, const Blk& b) {
+  i64 s = 0;
+  for (i64 r = b.r0; r < b.r1; ++r) s += row_count(R, r, b.c0, b.c1 - 1);
+  return s;
+}
+
+// Remove claimed entries: the new residual keeps the unclaimed ones in order.
+Mat compact(const Mat& R, const std::vector<char>& claimed) {
+  Mat N;
+  N.nrows = R.nrows;
+  N.ncols = R.ncols;
+  N.ptr.assign(R.nrows + 1, 0);
+  for (i64 i = 0; i < R.nrows; ++i) {
+    for (i64 k = R.ptr[i]; k < R.ptr[i + 1]; ++k) {
+      if (claimed[k]) continue;
+      N.col.push_back(R.col[k]);
+      N.val.push_back(R.val[k]);
+      N.id.push_back(R.id[k]);
+    }
+    N.ptr[i + 1] = (i64)N.col.size();
+  }
+  return N;
+}
+
+// Exact density comparison n1/a1 > n2/a2 (areas positive).
+bool dens_gt(i64 n1, i64 a1, i64 n2, i64 a2) {
+  return (__int128)n1 * a2 > (__int128)n2 * a1;
+}
+
+bool dense_enough(i64 nnz, i64 area, int p) {  // nnz/area >= p/1000
+  return (__int128)1000 * nnz >= (__int128)p * area;
+}
+
+// ---------------------------------------------------------------------------------------
+// Band extractor (Sec. 4.2; Alg. 3 and Alg. 4)
+
+// FitRibbon (Alg. 3): the paper only says it finds how many diagonals below and above d can
+// be included at row i while the ribbon stays delta-dense. Reading: grow greedily by the
+// nearest present cell on either side (smaller gap first, lower side first on ties) while
+// (present cells) / (ribbon width) >= delta; the width is capped at wmax per side.
+void fit_ribbon(const Mat& R, i64 i, i64 d, int p, i64 wmax, i64& l, i64& u, i64& k) {
+  l = u = k = 0;
+  if (!present(R, i, i + d)) return;
+  k = 1;
+  for (;;) {
+    i64 glo = 0, ghi = 0;  // 0 means "no present cell within the cap"
+    for (i64 g = 1; l + g <= wmax; ++g)
+      if (present(R, i, i + d - l - g)) { glo = g; break; }
+    for (i64 g = 1; u + g <= wmax; ++g)
+      if (present(R, i, i + d + u + g)) { ghi = g; break; }
+    // candidate list: (gap, side) with side 0 = below (lower offsets), 1 = above
+    std::vector<std::pair<i64, int>> cand;
+    if (glo) cand.push_back({glo, 0});
+    if (ghi) cand.push_back({ghi, 1});
+    std::sort(cand.begin(), cand.end());
+    bool applied = false;
+    for (auto& c : cand) {
+      if (dense_enough(k + 1, l + u + 1 + c.first, p)) {
+        if (c.second == 0) l += c.first; else u += c.first;
+        k += 1;
+        applied = true;
+        break;
+      }
+    }
+    if (!applied) break;
+  }
+}
+
+// GrowSegments (Alg. 4) for one candidate diagonal d. rows[] lists, in increasing order, the
+// rows whose centre cell (i, i+d) is present; l/u/k hold FitRibbon's result for them. Rows not
+// in the list have k = 0, so the algorithm's first branch skips them and runs of k > 0 are
+// runs of consecutive listed rows.
+void grow_segments(const Mat& R, i64 d, int p, i64 lseg, const std::vector<i64>& rows,
+                   const std::vector<i64>& l, const std::vector<i64>& u,
+                   const std::vector<i64>& k, std::vector<Seg>& S) {
+  const i64 n = R.nrows;
+  size_t q = 0;
+  while (q < rows.size()) {
+    if (k[q] == 0) { ++q; continue; }
+    i64 i0 = rows[q], L = l[q], U = u[q];
+    i64 z = row_count(R, i0, i0 + d - L, i0 + d + U);
+    size_t qj = q + 1;
+    i64 j = i0 + 1;
+    while (j < n && qj < rows.size() && rows[qj] == j && k[qj] > 0) {
+      i64 L2 = std::max(L, l[qj]), U2 = std::max(U, u[qj]);
+      i64 z2;
+      if (L2 != L || U2 != U) {
+        z2 = 0;  // exact recount over rows i0..j with the widened extents
+        for (i64 r = i0; r <= j; ++r) z2 += row_count(R, r, r + d - L2, r + d + U2);
+      } else {
+        z2 = z + row_count(R, j, j + d - L, j + d + U);
+      }
+      i64 area = (L2 + U2 + 1) * (j - i0 + 1);
+      if (!dense_enough(z2, area, p)) break;
+      L = L2; U = U2; z = z2;
+      ++qj; ++j;
+    }
+    if (j - i0 >= lseg) S.push_back({i0, j, L, U, z, d});
+    q = qj;  // i <- j: resume at row j (the first listed row >= j)
+  }
+}
+
+std::vector<Seg> extract_bands(const Mat& R, const Thr& th) {
+  const int p = th.delta_band_pm;
+  const i64 tau = th.lseg;  // count threshold reading: a kept segment has >= l_seg centres
+  // M[d]: nonzeros on diagonal d (j - i = d), and the rows carrying them in order.
+  std::map<i64, std::vector<i64>> diag_rows;
+  for (i64 i = 0; i < R.nrows; ++i)
+    for (i64 k = R.ptr[i]; k < R.ptr[i + 1]; ++k) {
+      i64 d = (i64)R.col[k] - i;
+      if (th.dmax >= 0 && (d > th.dmax || d < -th.dmax)) continue;
+      diag_rows[d].push_back(i);
+    }
+  std::vector<std::pair<i64, i64>> D;  // (-count, d): count descending, d ascending
+  for (auto& kv : diag_rows)
+    if ((i64)kv.second.size() >= tau) D.push_back({-(i64)kv.second.size(), kv.first});
+  std::sort(D.begin(), D.end());
+  std::vector<char> used(R.nrows, 0);
+  std::vector<Seg> accepted;
+  for (auto& cd : D) {
+    const i64 d = cd.second;
+    const std::vector<i64>& rows = diag_rows[d];
+    std::vector<i64> l(rows.size()), u(rows.size()), k(rows.size());
+    for (size_t q = 0; q < rows.size(); ++q) {
+      if (used[rows[q]]) { l[q] = u[q] = k[q] = 0; continue; }
+      fit_ribbon(R, rows[q], d, p, th.wmax, l[q], u[q], k[q]);
+    }
+    std::vector<Seg> S;
+    grow_segments(R, d, p, th.lseg, rows, l, u, k, S);
+    if (S.empty()) continue;
+    i64 area = 0, z = 0;
+    for (auto& s : S) { area += (s.L + s.U + 1) * (s.j - s.i0); z += s.z; }
+    if (area < th.amin_band || !dense_enough(z, area, p)) continue;
+    for (auto& s : S) {
+      for (i64 r = s.i0; r < s.j; ++r) used[r] = 1;
+      accepted.push_back(s);
+    }
+  }
+  std::sort(accepted.begin(), accepted.end(),
+            [](const Seg& a, const Seg& b) { return a.i0 < b.i0; });
+  return accepted;
+}
+
+// ---------------------------------------------------------------------------------------
+// Block extractor, literal search (Sec. 4.1; Alg. 1 and Alg. 2)
+
+struct Cand { i64 nnz = -1, area = 0, o0 = 0, o1 = 0, i0 = 0, i1 = 0; };
+
+// score(B) = area * (density - 0.5)^1.5 compared exactly: score^2 = (2n - a)^3 / (8a), so
+// score1 > score2 <=> (2n1 - a1)^3 * a2 > (2n2 - a2)^3 * a1. An empty candidate scores -1.
+bool score_gt(i64 n1, i64 a1, i64 n2, i64 a2) {
+  if (n1 < 0) return false;
+  if (n2 < 0) return true;
+  u128 t1 = (u128)(2 * n1 - a1);
+  u128 t2 = (u128)(2 * n2 - a2);
+  return t1 * t1 * t1 * (u128)a2 > t2 * t2 * t2 * (u128)a1;
+}
+
+i64 ceil_sqrt(i64 a) {
+  i64 s = 0;
+  while (s * s < a) ++s;
+  return s;
+}
+
+// FindBlock (Alg. 2) over region [r0,r1) x [c0,c1). by_rows selects the CSR pass (outer =
+// rows, inner = columns) or the CSC pass (outer = columns, inner = rows). Indices are
+// region-relative. The outer loop is the paper's parallel for; per-start results are merged
+// in start order with a strict comparison, which equals the sequential iteration.
+Cand find_block(const Mat& R, const Csc& C, const Blk& reg, bool by_rows, const Thr& th) {
+  const i64 Lout = by_rows ? reg.r1 - reg.r0 : reg.c1 - reg.c0;
+  const i64 Lin = by_rows ? reg.c1 - reg.c0 : reg.r1 - reg.r0;
+  const i64 amin = th.amin_block;
+  const int p = th.delta_block_pm;
+  const i64 smin = ceil_sqrt(amin);
+  std::vector<Cand> per(Lout > 0 ? Lout : 0);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (i64 o0 = 0; o0 < Lout; ++o0) {
+    std::vector<i64> H(Lin, 0);
+    Cand best;
+    for (i64 o1 = o0; o1 < Lout; ++o1) {
+      if (by_rows) {
+        i64 r = reg.r0 + o1;
+        const int32_t* b = R.col.data() + R.ptr[r];
+        const int32_t* e = R.col.data() + R.ptr[r + 1];
+        for (const int32_t* q = std::lower_bound(b, e, (int32_t)reg.c0); q < e && *q < reg.c1; ++q)
+          H[*q - reg.c0] += 1;
+      } else {
+        i64 c = reg.c0 + o1;
+        const int32_t* b = C.row.data() + C.ptr[c];
+        const int32_t* e = C.row.data() + C.ptr[c + 1];
+        for (const int32_t* q = std::lower_bound(b, e, (int32_t)reg.r0); q < e && *q < reg.r1; ++q)
+          H[*q - reg.r0] += 1;
+      }
+      const i64 s = o1 - o0 + 1;
+      if (s < smin) continue;
+      i64 nnz = 0, i0 = 0;
+      for (i64 i1 = 0; i1 < Lin; ++i1) {
+        nnz += H[i1];
+        while (i0 <= i1) {
+          const i64 a = s * (i1 - i0 + 1);
+          if (a < amin) break;
+          if (dense_enough(nnz, a, p)) {
+            if (score_gt(nnz, a, best.nnz, best.area)) {
+              best.nnz = nnz; best.area = a;
+              best.o0 = o0; best.o1 = o1; best.i0 = i0; best.i1 = i1;
+            }
+            break;
+          }
+          nnz -= H[i0];
+          i0 += 1;
+        }
+      }
+    }
+    per[o0] = best;
+  }
+  Cand best;
+  for (i64 o0 = 0; o0 < Lout; ++o0)
+    if (score_gt(per[o0].nnz, per[o0].area, best.nnz, best.area)) best = per[o0];
+  return best;
+}
+
+Blk cand_rect(const Cand& c, const Blk& reg, bool by_rows) {
+  if (by_rows) return {reg.r0 + c.o0, reg.r0 + c.o1 + 1, reg.c0 + c.i0, reg.c0 + c.i1 + 1};
+  return {reg.r0 + c.i0, reg.r0 + c.i1 + 1, reg.c0 + c.o0, reg.c0 + c.o1 + 1};
+}
+
+// Trim (Alg. 1): while removing one edge row/column strictly raises the block density,
+// remove the edge giving the highest density (ties: top, bottom, left, right).
+void trim(const Mat& R, const Csc& C, Blk& b, i64& nnz) {
+  for (;;) {
+    const i64 h = b.r1 - b.r0, w = b.c1 - b.c0, area = h * w;
+    int best_e = -1;
+    i64 bn = nnz, ba = area;  // current density is the bar to beat
+    for (int e = 0; e < 4; ++e) {
+      i64 cnt, len;
+      if (e == 0) { if (h < 2) continue; cnt = row_count(R, b.r0, b.c0, b.c1 - 1); len = w; }
+      else if (e == 1) { if (h < 2) continue; cnt = row_count(R, b.r1 - 1, b.c0, b.c1 - 1); len = w; }
+      else if (e == 2) { if (w < 2) continue; cnt = col_count(R, C, b.c0, b.r0, b.r1 - 1); len = h; }
+      else { if (w < 2) continue; cnt = col_count(R, C, b.c1 - 1, b.r0, b.r1 - 1); len = h; }
+      const i64 n2 = nnz - cnt, a2 = area - len;
+      if (dens_gt(n2, a2, bn, ba)) { best_e = e; bn = n2; ba = a2; }
+    }
+    if (best_e < 0) return;
+    if (best_e == 0) b.r0 += 1;
+    else if (best_e == 1) b.r1 -= 1;
+    else if (best_e == 2) b.c0 += 1;
+    else b.c1 -= 1;
+    nnz = bn;
+  }
+}
+
+struct PaperState {
+  const Mat* R;
+  const Csc* C;
+  const Thr* th;
+  std::vector<char> used_r, used_c;
+  std::vector<Blk> out;
+};
+
+// Decompose (Alg. 1): depth-first, in the order above, below, left, right.
+void decompose(PaperState& st, Blk reg) {
+  const Thr& th = *st.th;
+  if (reg.r1 <= reg.r0 || reg.c1 <= reg.c0) return;
+  if ((reg.r1 - reg.r0) * (reg.c1 - reg.c0) < th.amin_block) return;
+  Cand b = find_block(*st.R, *st.C, reg, true, th);
+  Cand b2 = find_block(*st.R, *st.C, reg, false, th);
+  bool use_csc = score_gt(b2.nnz, b2.area, b.nnz, b.area);
+  Cand bc = use_csc ? b2 : b;
+  if (bc.nnz < 0 || bc.area < th.amin_block) return;
+  Blk B = cand_rect(bc, reg, !use_csc);
+  for (i64 r = B.r0; r < B.r1; ++r) if (st.used_r[r]) return;
+  for (i64 c = B.c0; c < B.c1; ++c) if (st.used_c[c]) return;
+  i64 nnz = rect_nnz(*st.R, B);
+  trim(*st.R, *st.C, B, nnz);
+  const i64 area = (B.r1 - B.r0) * (B.c1 - B.c0);
+  if (!dense_enough(nnz, area, th.delta_block_pm) || area < th.amin_block) return;
+  st.out.push_back(B);
+  for (i64 r = B.r0; r < B.r1; ++r) st.used_r[r] = 1;
+  for (i64 c = B.c0; c < B.c1; ++c) st.used_c[c] = 1;
+  decompose(st, {reg.r0, B.r0, reg.c0, reg.c1});
+  decompose(st, {B.r1, reg.r1, reg.c0, reg.c1});
+  decompose(st, {B.r0, B.r1, reg.c0, B.c0});
+  decompose(st, {B.r0, B.r1, B.c1, reg.c1});
+}
+
+bool paper_mode_fits(i64 nrows, i64 ncols) {
+  const u128 m = (u128)std::max(nrows, ncols);
+  return (u128)nrows * (u128)ncols * m <= ((u128)1 << 37);
+}
+
+std::vector<Blk> extract_blocks_paper(const Mat& R, const Thr& th) {
+  Csc C = transpose(R);
+  PaperState st;
+  st.R = &R; st.C = &C; st.th = &th;
+  st.used_r.assign(R.nrows, 0);
+  st.used_c.assign(R.ncols, 0);
+  decompose(st, {0, R.nrows, 0, R.ncols});
+  std::vector<Blk> kept;
+  for (auto& b : st.out) if (b.c1 - b.c0 != 1) kept.push_back(b);  // drop width-1 blocks
+  return kept;
+}
+
+// ---------------------------------------------------------------------------------------
+// Block extractor, tiled delta-dense detection (scalable reading; not in the paper).
+// For tile size T: count entries per T x T tile, mark hot tiles (delta-dense, edge tiles
+// clipped), grow rectangles of hot unclaimed tiles greedily in row-major order (widest run
+// first, then as many rows as keep the whole run hot and unclaimed), then Trim and accept
+// each rectangle with the same density/area/width rules as the literal search.
+std::vector<Blk> tiled_for_T(const Mat& R, const Csc& C, const Thr& th, i64 T, i64& cov) {
+  const i64 ntr = (R.nrows + T - 1) / T, ntc = (R.ncols + T - 1) / T;
+  std::map<std::pair<i64, i64>, i64> cnt;
+  for (i64 i = 0; i < R.nrows; ++i)
+    for (i64 k = R.ptr[i]; k < R.ptr[i + 1]; ++k) cnt[{i / T, (i64)R.col[k] / T}] += 1;
+  std::map<std::pair<i64, i64>, char> hot;  // value: claimed flag
+  for (auto& kv : cnt) {
+    i64 I = kv.first.first, J = kv.first.second;
+    i64 h = std::min((I + 1) * T, R.nrows) - I * T;
+    i64 w = std::min((J + 1) * T, R.ncols) - J * T;
+    if (dense_enough(kv.second, h * w, th.delta_block_pm)) hot[{I, J}] = 0;
+  }
+  auto avail = [&](i64 I, i64 J) {
+    if (I >= ntr || J >= ntc) return false;
+    auto it = hot.find({I, J});
+    return it != hot.end() && it->second == 0;
+  };
+  std::vector<Blk> rects;
+  for (auto& kv : hot) {
+    if (kv.second) continue;
+    const i64 I = kv.first.first, J = kv.first.second;
+    i64 w = 1;
+    while (avail(I, J + w)) ++w;
+    i64 h = 1;
+    for (;;) {
+      bool ok = true;
+      for (i64 t = 0; t < w && ok; ++t) ok = avail(I + h, J + t);
+      if (!ok) break;
+      ++h;
+    }
+    for (i64 a = 0; a < h; ++a)
+      for (i64 t = 0; t < w; ++t) hot[{I + a, J + t}] = 1;
+    rects.push_back({I * T, std::min((I + h) * T, R.nrows), J * T, std::min((J + w) * T, R.ncols)});
+  }
+  std::vector<Blk> out;
+  cov = 0;
+  for (auto b : rects) {
+    i64 nnz = rect_nnz(R, b);
+    trim(R, C, b, nnz);
+    const i64 area = (b.r1 - b.r0) * (b.c1 - b.c0);
+    if (!dense_enough(nnz, area, th.delta_block_pm) || area < th.amin_block || b.c1 - b.c0 < 2)
+      continue;
+    out.push_back(b);
+    cov += nnz;
+  }
+  return out;
+}
+
+std::vector<Blk> extract_blocks_tiled(const Mat& R, const Thr& th, int32_t& chosen_T) {
+  static const i64 Ts[5] = {4, 6, 8, 16, 32};
+  Csc C = transpose(R);
+  i64 best_cov = -1;
+  std::vector<Blk> best;
+  chosen_T = 0;
+  for (int t = 0; t < 5; ++t) {
+    if (th.tile_set_mask && !(th.tile_set_mask & (1 << t))) continue;
+    i64 cov;
+    std::vector<Blk> b = tiled_for_T(R, C, th, Ts[t], cov);
+    if (cov >= best_cov) { best_cov = cov; best = b; chosen_T = (int32_t)Ts[t]; }  // ties: larger T
+  }
+  return best;
+}
+
+// ---------------------------------------------------------------------------------------
+// Plan (Sec. 3): run the extractors in order on the residual.
+
+enum { K_VDIA = 1, K_VBR = 2, K_CSR = 3 };
+
+int build_plan(i64 nrows, i64 ncols, i64 nnz, const i64* indptr, const int32_t* indices,
+               const float* values, const int32_t* kinds, const int32_t* modes, int nlist,
+               const Thr& th, Plan& P) {
+  if (nlist < 1 || kinds[nlist - 1] != K_CSR) return 3;  // incomplete: no catch-all last
+  for (int e = 0; e < nlist - 1; ++e) {
+    if (kinds[e] != K_VDIA && kinds[e] != K_VBR) return 1;
+    for (int f = 0; f < e; ++f) if (kinds[f] == kinds[e]) return 1;
+  }
+  P.nrows = nrows;
+  P.ncols = ncols;
+  Mat R;
+  R.nrows = nrows;
+  R.ncols = ncols;
+  R.ptr.assign(indptr, indptr + nrows + 1);
+  R.col.assign(indices, indices + nnz);
+  R.val.assign(values, values + nnz);
+  R.id.resize(nnz);
+  for (i64 k = 0; k < nnz; ++k) R.id[k] = k;
+  P.owner.assign(nnz, -1);
+  P.slot.assign(nnz, -1);
+  for (int e = 0; e < nlist; ++e) {
+    std::vector<char> claimed(R.nnz(), 0);
+    if (kinds[e] == K_VDIA) {
+      std::vector<Seg> S = extract_bands(R, th);
+      i64 vp = 0;
+      for (auto& s : S) {
+        const i64 nr = s.j - s.i0, nd = s.L + s.U + 1;
+        P.seg_row_start.push_back((int32_t)s.i0);
+        P.seg_nrows.push_back((int32_t)nr);
+        P.seg_ndiags.push_back((int32_t)nd);
+        P.seg_val_ptr.push_back(vp);
+        P.seg_idiag_ptr.push_back((int32_t)P.idiag.size());
+        for (i64 t = 0; t < nd; ++t) P.idiag.push_back((int32_t)(s.d - s.L + t));
+        P.vdia_val.resize(vp + nr * nd, 0.0f);
+        for (i64 r = s.i0; r < s.j; ++r) {
+          for (i64 k = R.ptr[r]; k < R.ptr[r + 1]; ++k) {
+            const i64 o = (i64)R.col[k] - r;
+            if (o < s.d - s.L || o > s.d + s.U) continue;
+            const i64 t = o - (s.d - s.L);
+            const i64 at = vp + t * nr + (r - s.i0);  // diagonal-major within the segment
+            P.vdia_val[at] = R.val[k];
+            claimed[k] = 1;
+            P.owner[R.id[k]] = 0;
+            P.slot[R.id[k]] = at;
+          }
+        }
+        vp += nr * nd;
+      }
+    } else if (kinds[e] == K_VBR) {
+      int mode = modes[e];
+      if (mode == 0) mode = paper_mode_fits(nrows, ncols) ? 1 : 2;
+      if (mode == 1 && !paper_mode_fits(nrows, ncols)) return 4;
+      std::vector<Blk> B;
+      int32_t T = 0;
+      if (mode == 1) B = extract_blocks_paper(R, th);
+      else B = extract_blocks_tiled(R, th, T);
+      i64 cov = 0;
+      for (auto& b : B) cov += rect_nnz(R, b);
+      if ((__int128)1000 * cov < (__int128)th.coverage_pm * R.nnz()) B.clear();  // cutoff
+      std::sort(B.begin(), B.end(), [](const Blk& a, const Blk& b) {
+        return a.r0 != b.r0 ? a.r0 < b.r0 : a.c0 < b.c0;
+      });
+      P.vbr_mode_used = mode;
+      P.vbr_tile = T;
+      i64 vp = 0;
+      for (auto& b : B) {
+        const i64 h = b.r1 - b.r0, w = b.c1 - b.c0;
+        P.blk.push_back((int32_t)b.r0); P.blk.push_back((int32_t)b.r1);
+        P.blk.push_back((int32_t)b.c0); P.blk.push_back((int32_t)b.c1);
+        P.blk_val_ptr.push_back(vp);
+        P.vbr_val.resize(vp + h * w, 0.0f);
+        for (i64 r = b.r0; r < b.r1; ++r) {
+          for (i64 k = R.ptr[r]; k < R.ptr[r + 1]; ++k) {
+            const i64 c = R.col[k];
+            if (c < b.c0 || c >= b.c1) continue;
+            const i64 at = vp + (c - b.c0) * h + (r - b.r0);  // column-major within the block
+            P.vbr_val[at] = R.val[k];
+            claimed[k] = 1;
+            P.owner[R.id[k]] = 1;
+            P.slot[R.id[k]] = at;
+          }
+        }
+        vp += h * w;
+      }
+    } else {
+      P.csr_ptr = R.ptr;
+      P.csr_col = R.col;
+      P.csr_val = R.val;
+      for (i64 k = 0; k < R.nnz(); ++k) {
+        claimed[k] = 1;
+        P.owner[R.id[k]] = 2;
+        P.slot[R.id[k]] = k;
+      }
+    }
+    R = compact(R, claimed);
+  }
+  return 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// C interface used by oracle/__init__.py
+
+extern "C" {
+
+// 0 = canonical CSR (indptr starts at 0, is non-decreasing, ends at nnz; columns in range
+// and strictly increasing within each row); 2 = invalid.
+int sor_validate(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* indptr,
+                 const int32_t* indices) {
+  if (nrows < 0 || ncols < 0 || nnz < 0) return 1;
+  if (indptr[0] != 0 || indptr[nrows] != nnz) return 2;
+  for (int64_t i = 0; i < nrows; ++i) {
+    if (indptr[i + 1] < indptr[i]) return 2;
+    for (int64_t k = indptr[i]; k < indptr[i + 1]; ++k) {
+      if (indices[k] < 0 || indices[k] >= ncols) return 2;
+      if (k > indptr[i] && indices[k] <= indices[k - 1]) return 2;
+    }
+  }
+  return 0;
+}
+
+int sor_plan(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* indptr,
+             const int32_t* indices, const float* values, const int32_t* kinds,
+             const int32_t* modes, int32_t nlist, const Thr* th, void** out) {
+  *out = nullptr;
+  if (th->delta_block_pm < 500 || th->delta_block_pm > 1000 || th->delta_band_pm < 1 ||
+      th->delta_band_pm > 1000 || th->amin_block < 1 || th->amin_band < 1 || th->lseg < 1 ||
+      th->wmax < 0)
+    return 1;
+  int v = sor_validate(nrows, ncols, nnz, indptr, indices);
+  if (v) return v;
+  Plan* P = new (std::nothrow) Plan();
+  if (!P) return 5;
+  int rc = build_plan(nrows, ncols, nnz, indptr, indices, values, kinds, modes, nlist, *th, *P);
+  if (rc) { delete P; return rc; }
+  *out = P;
+  return 0;
+}
+
+// counts: [nseg, vdia_nval, nidiag, nblk, vbr_nval, csr_nnz, vbr_tile, vbr_mode_used]
+void sor_counts(void* h, int64_t* c) {
+  Plan* P = (Plan*)h;
+  c[0] = (int64_t)P->seg_row_start.size();
+  c[1] = (int64_t)P->vdia_val.size();
+  c[2] = (int64_t)P->idiag.size();
+  c[3] = (int64_t)P->blk_val_ptr.size();
+  c[4] = (int64_t)P->vbr_val.size();
+  c[5] = (int64_t)P->csr_col.size();
+  c[6] = P->vbr_tile;
+  c[7] = P->vbr_mode_used;
+}
+
+void sor_export(void* h, float* vdia_val, int32_t* idiag, int32_t* seg_row_start,
+                int32_t* seg_nrows, int32_t* seg_ndiags, int64_t* seg_val_ptr,
+                int32_t* seg_idiag_ptr, int32_t* blk, int64_t* blk_val_ptr, float* vbr_val,
+                int64_t* csr_ptr, int32_t* csr_col, float* csr_val, int8_t* owner,
+                int64_t* slot) {
+  Plan* P = (Plan*)h;
+  put(vdia_val, P->vdia_val); put(idiag, P->idiag); put(seg_row_start, P->seg_row_start);
+  put(seg_nrows, P->seg_nrows); put(seg_ndiags, P->seg_ndiags); put(seg_val_ptr, P->seg_val_ptr);
+  put(seg_idiag_ptr, P->seg_idiag_ptr); put(blk, P->blk); put(blk_val_ptr, P->blk_val_ptr);
+  put(vbr_val, P->vbr_val); put(csr_ptr, P->csr_ptr); put(csr_col, P->csr_col);
+  put(csr_val, P->csr_val); put(owner, P->owner); put(slot, P->slot);
+}
+
+void sor_free(void* h) { delete (Plan*)h; }
+
+void sor_set_threads(int32_t n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
+int32_t sor_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+// y = A x in FP64, each row summed in stored (column-ascending) order (Sec. 5 "Kernels").
+// Rows are independent, so splitting rows across threads does not change any result.
+void sor_spmv_f64(int64_t nrows, const int64_t* indptr, const int32_t* indices,
+                  const float* values, const float* x, double* y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nrows; ++i) {
+    double s = 0.0;
+    for (int64_t k = indptr[i]; k < indptr[i + 1]; ++k) s += (double)values[k] * (double)x[indices[k]];
+    y[i] = s;
+  }
+}
+
+// y[rows[t]] for a list of rows only (sampled checks at full size).
+void sor_spmv_rows_f64(int64_t nsel, const int64_t* rows, const int64_t* indptr,
+                       const int32_t* indices, const float* values, const float* x, double* y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < nsel; ++t) {
+    const int64_t i = rows[t];
+    double s = 0.0;
+    for (int64_t k = indptr[i]; k < indptr[i + 1]; ++k) s += (double)values[k] * (double)x[indices[k]];
+    y[t] = s;
+  }
+}
+
+// Y = A X with X (ncols x n) and Y (nrows x n) row-major (App. A.2 layout), FP64.
+void sor_spmm_f64(int64_t nrows, const int64_t* indptr, const int32_t* indices,
+                  const float* values, const float* X, int64_t n, double* Y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nrows; ++i) {
+    double* yr = Y + i * n;
+    for (int64_t c = 0; c < n; ++c) yr[c] = 0.0;
+    for (int64_t k = indptr[i]; k < indptr[i + 1]; ++k) {
+      const double a = (double)values[k];
+      const float* xr = X + (int64_t)indices[k] * n;
+      for (int64_t c = 0; c < n; ++c) yr[c] += a * (double)xr[c];
+    }
+  }
+}
+
+void sor_spmm_rows_f64(int64_t nsel, const int64_t* rows, const int64_t* indptr,
+                       const int32_t* indices, const float* values, const float* X, int64_t n,
+                       double* Y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < nsel; ++t) {
+    const int64_t i = rows[t];
+    double* yr = Y + t * n;
+    for (int64_t c = 0; c < n; ++c) yr[c] = 0.0;
+    for (int64_t k = indptr[i]; k < indptr[i + 1]; ++k) {
+      const double a = (double)values[k];
+      const float* xr = X + (int64_t)indices[k] * n;
+      for (int64_t c = 0; c < n; ++c) yr[c] += a * (double)xr[c];
+    }
+  }
+}
+
+// y = (VDIA part + VBR part + CSR part) x in FP64 from a plan's formats, fill included and
+// out-of-range band cells skipped. Differs from sor_spmv_f64 only by FP64 rounding order.
+void sor_partition_spmv_f64(void* h, const float* x, double* y) {
+  Plan* P = (Plan*)h;
+  for (int64_t i = 0; i < P->nrows; ++i) y[i] = 0.0;
+  for (size_t s = 0; s < P->seg_row_start.size(); ++s) {
+    const int64_t r0 = P->seg_row_start[s], nr = P->seg_nrows[s], nd = P->seg_ndiags[s];
+    for (int64_t t = 0; t < nd; ++t) {
+      const int64_t o = P->idiag[P->seg_idiag_ptr[s] + t];
+      for (int64_t r = 0; r < nr; ++r) {
+        const int64_t c = r0 + r + o;
+        if (c < 0 || c >= P->ncols) continue;
+        y[r0 + r] += (double)P->vdia_val[P->seg_val_ptr[s] + t * nr + r] * (double)x[c];
+      }
+    }
+  }
+  for (size_t b = 0; b < P->blk_val_ptr.size(); ++b) {
+    const int64_t r0 = P->blk[4 * b], r1 = P->blk[4 * b + 1], c0 = P->blk[4 * b + 2], c1 = P->blk[4 * b + 3];
+    const int64_t h = r1 - r0;
+    for (int64_t c = c0; c < c1; ++c)
+      for (int64_t r = r0; r < r1; ++r)
+        y[r] += (double)P->vbr_val[P->blk_val_ptr[b] + (c - c0) * h + (r - r0)] * (double)x[c];
+  }
+  for (int64_t i = 0; i < P->nrows; ++i)
+    for (int64_t k = P->csr_ptr[i]; k < P->csr_ptr[i + 1]; ++k)
+      y[i] += (double)P->csr_val[k] * (double)x[P->csr_col[k]];
+}
+
+// Round-to-nearest-even fp32 -> bf16 split: hi = bf16(a), lo = bf16(a - hi). a - hi is
+// exact in fp32 (Sterbenz-style: hi shares a's exponent range), so hi + lo carries 16
+// significant bits of a.
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+static float bf16_to_f32(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+void sor_bf16_split(int64_t n, const float* a, uint16_t* hi, uint16_t* lo) {
+  for (int64_t i = 0; i < n; ++i) {
+    hi[i] = bf16_rne(a[i]);
+    lo[i] = bf16_rne(a[i] - bf16_to_f32(hi[i]));
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,377 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix (no GPU).
+
+Each test names the passage it pins. A plausible slip in the oracle (a dropped term, an
+off-by-one in a segment bound, > for >=, a transposed layout) fails at least one of them.
+"""
+import fractions
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2407_00829_amd.synth import from_coo, gen_random_small
+from tests.conftest import read_golden
+
+V, B, C = oracle.VDIA, oracle.VBR, oracle.CSR
+
+
+def dense_to_csr(D):
+    r, c = np.nonzero(D)
+    return from_coo(D.shape[0], D.shape[1], r, c, D[r, c])
+
+
+# --- Sec. 4.2.1, Fig. "vdia": the worked VDIA example --------------------------------
+
+def test_fig_vdia_arrays_exact():
+    g = read_golden("fig_vdia.txt")
+    D = np.zeros((g["nrows"][0], g["ncols"][0]), np.float32)
+    for r, ents in g["rows"].items():
+        for c, v in ents:
+            D[r, c] = v
+    A = dense_to_csr(D)
+    # l_seg <= 3, A_min <= 12 and count threshold <= 3 let both 3- and 4-row segments pass
+    for p in (500, 750, 1000):
+        P = oracle.plan(A, [V, C], th=oracle.Thresholds(delta_band_pm=p, lseg=3, amin_band=12))
+        assert P["vdia_val"].tolist() == [float(t) for t in g["val"]]
+        assert P["idiag"].tolist() == g["idiag"]
+        assert P["seg_row_start"].tolist() == g["seg_row_start"]
+        assert P["seg_nrows"].tolist() == g["seg_nrows"]
+        assert P["seg_ndiags"].tolist() == g["seg_ndiags"]
+        assert P["seg_val_ptr"].tolist() == g["seg_val_ptr"]
+        assert P["seg_idiag_ptr"].tolist() == g["seg_idiag_ptr"]
+        assert P["csr_col"].size == 0
+
+
+def test_fig_vdia_lseg_gate():
+    """A segment needs at least l_seg rows (Alg. 4): with l_seg = 4 only segment 0 stays."""
+    g = read_golden("fig_vdia.txt")
+    D = np.zeros((10, 10), np.float32)
+    for r, ents in g["rows"].items():
+        for c, v in ents:
+            D[r, c] = v
+    P = oracle.plan(dense_to_csr(D), [V, C], th=oracle.Thresholds(lseg=4, amin_band=12))
+    assert P["seg_row_start"].tolist() == [1] and P["seg_nrows"].tolist() == [4]
+    assert P["csr_col"].size == 12
+
+
+# --- App. B, Fig. "vbr": the worked VBR example --------------------------------------
+
+def _fig_vbr():
+    g = read_golden("fig_vbr.txt")
+    return g, np.array(g["dense"], np.float32)
+
+
+def test_fig_vbr_sparskit_arrays_exact():
+    g, D = _fig_vbr()
+    Val, Indx, Bindx, Bpntrb = oracle.vbr_from_dense(D, g["Rpntr"], g["Cpntr"])
+    assert Val.tolist() == [float(v) for v in g["Val"]]
+    assert Indx.tolist() == g["Indx"]
+    assert Bindx.tolist() == g["Bindx"]
+    assert Bpntrb.tolist() == g["Bpntrb"]
+
+
+def test_fig_vbr_spmv_matches_brute_force():
+    g, D = _fig_vbr()
+    x = np.arange(1, 12, dtype=np.float32) * np.float32(0.5) - 2
+    y = oracle.sparskit_spmv(np.array(g["Val"], np.float64), g["Indx"], g["Bindx"], g["Rpntr"],
+                             g["Cpntr"], g["Bpntrb"], x)
+    ref = D.astype(np.float64) @ x.astype(np.float64)
+    assert np.array_equal(y, ref)
+    # the COO oracle agrees with the same brute force
+    assert np.array_equal(oracle.spmv(dense_to_csr(D), x), ref)
+
+
+def test_export_to_sparskit_roundtrip_paper_blocks():
+    """Blocks of the literal search are row/column-disjoint, so they form a SPARSKIT grid
+    and the SPARSKIT product equals the dense product of the blocks."""
+    D = np.zeros((120, 120), np.float32)
+    rng = np.random.default_rng(3)
+    D[10:30, 40:70] = rng.uniform(-1, 1, (20, 30))
+    D[60:100, 5:25] = rng.uniform(-1, 1, (40, 20))
+    A = dense_to_csr(D)
+    P = oracle.plan(A, [B, C], oracle.MODE_PAPER, oracle.Thresholds(amin_block=100))
+    Val, Indx, Bindx, Rp, Cp, Bp = oracle.export_to_sparskit(P)
+    x = rng.uniform(-1, 1, 120).astype(np.float32)
+    assert np.allclose(oracle.sparskit_spmv(Val, Indx, Bindx, Rp, Cp, Bp, x),
+                       D.astype(np.float64) @ x, rtol=0, atol=1e-12)
+
+
+# --- Alg. 1 / Alg. 2 closed-form cases ------------------------------------------------
+
+def test_score_comparator_identity():
+    """score = area*(density-0.5)^1.5 ordered by the exact identity score^2=(2n-a)^3/(8a)."""
+    rng = np.random.default_rng(0)
+    for _ in range(400):
+        a1, a2 = (int(t) for t in rng.integers(1, 5000, 2))
+        n1 = int(rng.integers((a1 + 1) // 2, a1 + 1))
+        n2 = int(rng.integers((a2 + 1) // 2, a2 + 1))
+        s1 = fractions.Fraction(2 * n1 - a1) ** 3 / (8 * a1)
+        s2 = fractions.Fraction(2 * n2 - a2) ** 3 / (8 * a2)
+        f1 = a1 * (n1 / a1 - 0.5) ** 1.5
+        f2 = a2 * (n2 / a2 - 0.5) ** 1.5
+        if abs(f1 - f2) > 1e-9 * max(f1, f2, 1):
+            assert (s1 > s2) == (f1 > f2)
+
+
+def test_single_dense_block_found_exactly():
+    D = np.zeros((200, 200), np.float32)
+    D[30:90, 50:120] = 1.5
+    P = oracle.plan(dense_to_csr(D), [B, C], oracle.MODE_PAPER, oracle.Thresholds())
+    assert P["blk"].tolist() == [[30, 90, 50, 120]]
+    assert P["csr_col"].size == 0
+
+
+def test_disjoint_blocks_found_exactly():
+    D = np.zeros((300, 300), np.float32)
+    rects = [(0, 60, 200, 260), (100, 160, 0, 55), (200, 280, 100, 150)]
+    for r0, r1, c0, c1 in rects:
+        D[r0:r1, c0:c1] = 2.0
+    P = oracle.plan(dense_to_csr(D), [B, C], oracle.MODE_PAPER, oracle.Thresholds())
+    assert sorted(P["blk"].tolist()) == sorted([list(r) for r in rects])
+
+
+def test_density_exactly_delta_is_accepted():
+    """Acceptance is inclusive (Alg. 1 rejects only density < delta)."""
+    D = np.zeros((120, 120), np.float32)
+    D[10:70, 20:80] = 1.0
+    P = oracle.plan(dense_to_csr(D), [B, C], oracle.MODE_PAPER,
+                    oracle.Thresholds(delta_block_pm=1000))
+    assert P["blk"].tolist() == [[10, 70, 20, 80]]
+
+
+def test_width_one_block_discarded_height_one_kept():
+    """Alg. 1 discards single-column blocks; a single row is a legal block."""
+    D = np.zeros((3000, 8), np.float32)
+    D[:, 3] = 1.0
+    P = oracle.plan(dense_to_csr(D), [B, C], oracle.MODE_PAPER, oracle.Thresholds(coverage_pm=0))
+    assert P["blk"].shape[0] == 0
+    D = np.zeros((8, 3000), np.float32)
+    D[5, :] = 1.0
+    P = oracle.plan(dense_to_csr(D), [B, C], oracle.MODE_PAPER, oracle.Thresholds(coverage_pm=0))
+    assert P["blk"].tolist() == [[5, 6, 0, 3000]]
+
+
+@pytest.mark.parametrize("extra,kept", [(0, True), (1, False)])
+def test_coverage_cutoff_boundary(extra, kept):
+    """Alg. 1 rejects the blocks when they cover < 8% of the nonzeros: exactly 8% passes."""
+    n = 400
+    D = np.zeros((n, n), np.float32)
+    D[0:16, 0:16] = 1.0  # 256 block entries
+    rng = np.random.default_rng(1)
+    need = 256 * 1000 // 80 - 256 + extra  # 2944 (+1) scattered entries outside the block
+    cells = set()
+    while len(cells) < need:
+        i, j = (int(t) for t in rng.integers(20, n, 2))
+        cells.add((i, j))
+    for i, j in cells:
+        D[i, j] = 0.5
+    P = oracle.plan(dense_to_csr(D), [B, C], oracle.MODE_PAPER,
+                    oracle.Thresholds(amin_block=256))
+    assert (P["blk"].tolist() == [[0, 16, 0, 16]]) == kept
+    if not kept:
+        assert P["blk"].shape[0] == 0
+
+
+def test_trim_removes_sparse_edge():
+    """Trim (Alg. 1): a sparse edge row attached to a dense block is removed."""
+    D = np.zeros((100, 100), np.float32)
+    D[20:70, 20:70] = 1.0
+    D[70, 20:45] = 1.0  # a half-filled row below the block
+    P = oracle.plan(dense_to_csr(D), [B, C], oracle.MODE_PAPER, oracle.Thresholds())
+    assert P["blk"].tolist() == [[20, 70, 20, 70]]
+
+
+def test_paper_mode_budget():
+    A = from_coo(6000, 6000, [0], [0], [1.0])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.plan(A, [B, C], oracle.MODE_PAPER)
+    assert e.value.code == 4
+    P = oracle.plan(A, [B, C], oracle.MODE_AUTO)
+    assert P["vbr_mode"] == oracle.MODE_TILED
+
+
+# --- Alg. 3 / Alg. 4 closed-form cases -------------------------------------------------
+
+def band(n, d, rows, val=1.0):
+    rows = np.asarray(list(rows))
+    return rows, rows + d, np.full(rows.size, val, np.float32)
+
+
+def test_full_band_one_segment():
+    r, c, v = band(300, 5, range(10, 250))
+    A = from_coo(300, 300, r, c, v)
+    P = oracle.plan(A, [V, C], th=oracle.Thresholds(amin_band=64))
+    assert P["seg_row_start"].tolist() == [10] and P["seg_nrows"].tolist() == [240]
+    assert P["idiag"].tolist() == [5]
+
+
+def test_missing_centre_splits_segment():
+    rows = [i for i in range(200) if i != 100]
+    r, c, v = band(300, 0, rows)
+    P = oracle.plan(from_coo(300, 300, r, c, v), [V, C], th=oracle.Thresholds(amin_band=64))
+    assert P["seg_row_start"].tolist() == [0, 101]
+    assert P["seg_nrows"].tolist() == [100, 99]
+
+
+def test_segment_length_exactly_lseg_kept():
+    r, c, v = band(300, 0, range(0, 64))
+    P = oracle.plan(from_coo(300, 300, r, c, v), [V, C], th=oracle.Thresholds(amin_band=64))
+    assert P["seg_nrows"].tolist() == [64]
+    r, c, v = band(300, 0, range(0, 63))
+    P = oracle.plan(from_coo(300, 300, r, c, v), [V, C], th=oracle.Thresholds(amin_band=63))
+    assert P["seg_nrows"].size == 0
+
+
+def test_density_crossing_breaks_at_computed_row():
+    """Rows 0..m-1 carry diagonals {0,+1}, rows m.. only {0}. With delta = 0.75 the ribbon
+    [0,1] stays dense while (2m + t) / (2(m + t)) >= 3/4, i.e. t <= m: the segment breaks
+    at row 2m (exactly at delta it continues), and a single-diagonal segment follows."""
+    m = 100
+    r0, c0, v0 = band(500, 0, range(0, 400))
+    r1, c1, v1 = band(500, 1, range(0, m))
+    A = from_coo(500, 500, np.r_[r0, r1], np.r_[c0, c1], np.r_[v0, v1])
+    P = oracle.plan(A, [V, C], th=oracle.Thresholds(delta_band_pm=750, amin_band=64))
+    assert P["seg_row_start"].tolist() == [0, 2 * m]
+    assert P["seg_nrows"].tolist() == [2 * m, 400 - 2 * m]
+    assert P["seg_ndiags"].tolist() == [2, 1]
+
+
+def test_widening_recount_breaks():
+    """A row whose ribbon is wider forces an exact recount (Alg. 4) that breaks the run."""
+    r0, c0, v0 = band(300, 0, range(0, 300))
+    A = from_coo(300, 300, np.r_[r0, 150, 150], np.r_[c0, 148, 149], np.r_[v0, 1.0, 1.0])
+    P = oracle.plan(A, [V, C], th=oracle.Thresholds(amin_band=64))
+    assert P["seg_row_start"].tolist() == [0, 151]
+    assert P["seg_nrows"].tolist() == [150, 149]
+    assert P["csr_col"].size == 3
+
+
+def test_ribbon_bridges_gap_only_when_dense_enough():
+    """FitRibbon reading: cells at offsets {0, 2} give a 3-wide ribbon with a hole when
+    2/3 >= delta; otherwise the ribbon is the centre only and, rows being claimed whole, the
+    +2 diagonal is left to CSR."""
+    r0, c0, v0 = band(300, 0, range(0, 200))
+    r2, c2, v2 = band(300, 2, range(0, 200))
+    A = from_coo(300, 300, np.r_[r0, r2], np.r_[c0, c2], np.r_[v0, v2])
+    P = oracle.plan(A, [V, C], th=oracle.Thresholds(delta_band_pm=600, amin_band=64))
+    assert P["idiag"].tolist() == [0, 1, 2]
+    assert P["seg_nrows"].tolist() == [200]
+    P = oracle.plan(A, [V, C], th=oracle.Thresholds(delta_band_pm=750, amin_band=64))
+    assert P["idiag"].tolist() == [0]
+    assert P["csr_col"].size == 200
+
+
+def test_band_region_area_gate():
+    """Alg. 3 rejects a candidate whose segments cover less than A_min cells."""
+    r, c, v = band(300, 0, range(0, 100))
+    A = from_coo(300, 300, r, c, v)
+    assert oracle.plan(A, [V, C], th=oracle.Thresholds(amin_band=100))["seg_nrows"].tolist() == [100]
+    assert oracle.plan(A, [V, C], th=oracle.Thresholds(amin_band=101))["seg_nrows"].size == 0
+
+
+def test_row_mask_is_exclusive():
+    """Rows claimed by an accepted band are never revisited (Alg. 3 used mask)."""
+    r0, c0, v0 = band(300, 0, range(0, 200))
+    r1, c1, v1 = band(300, 40, range(0, 200))
+    A = from_coo(300, 300, np.r_[r0, r1], np.r_[c0, c1], np.r_[v0, v1])
+    P = oracle.plan(A, [V, C], th=oracle.Thresholds(amin_band=64))
+    assert P["idiag"].tolist() == [0]
+    assert P["csr_col"].size == 200
+
+
+# --- tiled block detection (reading, not in the paper) ---------------------------------
+
+def test_tiled_planted_aligned_blocks():
+    D = np.zeros((256, 256), np.float32)
+    D[32:96, 64:128] = 1.0
+    D[160:192, 0:64] = 1.0
+    P = oracle.plan(dense_to_csr(D), [B, C], oracle.MODE_TILED, oracle.Thresholds(amin_block=256))
+    assert sorted(P["blk"].tolist()) == [[32, 96, 64, 128], [160, 192, 0, 64]]
+    assert P["vbr_tile"] == 32
+
+
+def test_tiled_fem_strips():
+    """C3-style node blocks (no bands, no scatter): at T = 6 the greedy tiles every dense
+    6x6 node block; rows of three neighbouring blocks become 6x18 strips, and from the
+    periodic wrap a staircase of 18x6 strips propagates along the block diagonals. Either
+    way every rectangle is fully dense with 108 cells and nearly all entries are covered."""
+    from paper_2407_00829_amd.synth import gen_c3
+    A, _ = gen_c3(0, n=6 * 3000, ystride=44, zstride=400, scatter_density=0.0, with_x=False)
+    # remove the two random bands: keep entries inside node blocks only
+    P = oracle.plan(A, [B, C], oracle.MODE_TILED,
+                    oracle.Thresholds(delta_block_pm=900, amin_block=36, tile_set_mask=2))
+    blk = P["blk"]
+    area = (blk[:, 1] - blk[:, 0]) * (blk[:, 3] - blk[:, 2])
+    assert P["vbr_tile"] == 6
+    assert np.mean(area == 108) > 0.99
+    assert np.count_nonzero(P["vbr_val"]) >= 0.97 * P["vbr_val"].size
+    assert P["csr_col"].size < 0.01 * A.nnz
+
+
+# --- FP64 products against brute force -------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_spmv_spmm_brute_force(seed):
+    A = gen_random_small(seed, 37 + seed, 53, 0.08, nbands=2, nblocks=2)
+    D = np.zeros((A.nrows, A.ncols), np.float64)
+    D[A.rows(), A.indices] = A.values
+    x = np.random.default_rng(seed).uniform(-1, 1, A.ncols).astype(np.float32)
+    assert np.allclose(oracle.spmv(A, x), D @ x.astype(np.float64), rtol=0, atol=1e-13)
+    X = np.random.default_rng(seed + 9).uniform(-1, 1, (A.ncols, 5)).astype(np.float32)
+    assert np.allclose(oracle.spmm(A, X), D @ X.astype(np.float64), rtol=0, atol=1e-13)
+    rows = np.array([0, 3, A.nrows - 1])
+    assert np.array_equal(oracle.spmv_rows(A, x, rows), oracle.spmv(A, x)[rows])
+    assert np.array_equal(oracle.spmm_rows(A, X, rows), oracle.spmm(A, X)[rows])
+
+
+# --- exact cover on random matrices (Sec. 3 completeness) ------------------------------
+
+PLANS = [[C], [V, C], [B, C], [V, B, C], [B, V, C]]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_partition_invariants(seed):
+    A = gen_random_small(seed, 90, 80, 0.05, nbands=3, nblocks=3, block_max=24)
+    th = oracle.Thresholds(lseg=4, amin_band=8, amin_block=16, coverage_pm=20 * (seed % 3))
+    x = np.random.default_rng(seed).uniform(-1, 1, A.ncols).astype(np.float32)
+    ref = oracle.spmv(A, x)
+    for kinds in PLANS:
+        for mode in (oracle.MODE_PAPER, oracle.MODE_TILED):
+            P = oracle.plan(A, kinds, mode, th)
+            oracle.check_partition(A, P, th, kinds)
+            y = oracle.partition_spmv_from_export(P, x)
+            assert np.allclose(y, ref, rtol=0, atol=1e-12)
+
+
+def test_plan_errors():
+    A = gen_random_small(0, 20, 20, 0.1)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.plan(A, [V, B])
+    assert e.value.code == 3
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.plan(A, [C, V, C])
+    assert e.value.code == 1
+    bad = from_coo(3, 3, [0, 1], [0, 1], [1, 1])
+    bad.indices = np.array([1, 1], np.int32)
+    bad.indptr = np.array([0, 2, 2, 2])
+    assert oracle.validate(bad) == 2
+
+
+# --- BF16 split (split-precision SpMM operands) ----------------------------------------
+
+def test_bf16_split_matches_torch_rne():
+    rng = np.random.default_rng(5)
+    a = np.concatenate([rng.standard_normal(5000).astype(np.float32),
+                        np.array([0.0, -0.0, 1.0, 3.0e-39, 65504.0, 1 + 2 ** -8, 1 + 3 * 2 ** -9],
+                                 np.float32)])
+    hi, lo = oracle.bf16_split(a)
+    th = torch.from_numpy(a).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(hi, th)
+    rem = a - oracle.bf16_to_f32(hi)
+    tl = torch.from_numpy(rem).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(lo, tl)
+    recon = oracle.bf16_to_f32(hi).astype(np.float64) + oracle.bf16_to_f32(lo)
+    big = np.abs(a) > 1e-30
+    assert np.all(np.abs(recon[big] - a[big]) <= np.abs(a[big]) * 2.0 ** -16)
