@@ -1,0 +1,357 @@
+// C interface of libsable: plan construction (Sec. 3), export, value refresh, error norm.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "plan.h"
+
+namespace sable {
+
+const char* last_error();
+bool vbr_paper_fits(i64 nrows, i64 ncols);
+
+namespace {
+
+template <class F>
+sable_status guard(F&& f) {
+  clear_error();
+  try {
+    f();
+    return SABLE_OK;
+  } catch (const Err& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return SABLE_ERR_OOM;
+  } catch (...) {
+    set_error("internal error");
+    return SABLE_ERR_INTERNAL;
+  }
+}
+
+__global__ void k_csr_owner(const int32_t* __restrict__ rid, i64 n, int8_t* __restrict__ owner,
+                            i64* __restrict__ slot) {
+  for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x) {
+    owner[rid[k]] = 2;
+    slot[rid[k]] = k;
+  }
+}
+
+// Refresh every stored value from a new value array with the same structure.
+__global__ void k_update_values(const float* __restrict__ values, i64 nnz,
+                                const int8_t* __restrict__ owner, const i64* __restrict__ slot,
+                                float* __restrict__ vdia, float* __restrict__ vbr,
+                                float* __restrict__ csr, float* __restrict__ aval) {
+  for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < nnz; k += (i64)gridDim.x * blockDim.x) {
+    const float v = values[k];
+    const int8_t o = owner[k];
+    const i64 at = slot[k];
+    if (o == 0) vdia[at] = v;
+    else if (o == 1) vbr[at] = v;
+    else csr[at] = v;
+    aval[k] = v;
+  }
+}
+
+constexpr int kNormThreads = 256;
+
+__global__ __launch_bounds__(kNormThreads) void k_norm_partial(const float* __restrict__ y,
+                                                               const double* __restrict__ yref,
+                                                               i64 n, double* __restrict__ part) {
+  __shared__ double sd[kNormThreads], sr[kNormThreads];
+  double a = 0.0, b = 0.0;
+  for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x) {
+    const double d = (double)y[k] - yref[k];
+    a += d * d;
+    b += yref[k] * yref[k];
+  }
+  sd[threadIdx.x] = a;
+  sr[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sd[threadIdx.x] += sd[threadIdx.x + w];
+      sr[threadIdx.x] += sr[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sd[0];
+    part[2 * blockIdx.x + 1] = sr[0];
+  }
+}
+
+__global__ void k_norm_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x || blockIdx.x) return;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < nb; ++k) { a += part[2 * k]; b += part[2 * k + 1]; }
+  out[0] = a;
+  out[1] = b;
+}
+
+void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list, int nlist,
+                const sable_thresholds& th, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  P.nrows = A.nrows;
+  P.ncols = A.ncols;
+  P.nnz = A.nnz;
+  P.flags = th.flags;
+  P.owner.alloc(A.nnz);
+  P.slot.alloc(A.nnz);
+  // plain copy of the input (baseline CSR kernel and value refresh)
+  P.a_ptr.alloc(A.nrows + 1);
+  P.a_col.alloc(A.nnz);
+  P.a_val.alloc(A.nnz);
+  HIPC(hipMemcpyAsync(P.a_ptr.p, A.indptr, (A.nrows + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  if (A.nnz) {
+    HIPC(hipMemcpyAsync(P.a_col.p, A.indices, A.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPC(hipMemcpyAsync(P.a_val.p, A.values, A.nnz * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
+  Resid R;
+  resid_from_input(R, A, s);
+  for (int e = 0; e < nlist; ++e) {
+    if (list[e].kind == SABLE_X_CSR) {
+      extract_csr(P, R, s);
+      break;
+    }
+    DBuf<uint8_t> claimed(R.nnz);
+    if (R.nnz) HIPC(hipMemsetAsync(claimed.p, 0, R.nnz, s));
+    if (list[e].kind == SABLE_X_VDIA) extract_bands(P, R, th, claimed, s);
+    else extract_blocks(P, R, th, list[e].vbr_mode, claimed, s);
+    resid_compact(R, claimed, s);
+  }
+  if (P.vbr_cells && (P.flags & SABLE_F_SPLIT_BF16)) build_bf16_split(P, s);
+  build_schedule(P, P.sched, P.prm.spmv_rows_per_tile, true, s);
+  build_schedule(P, P.sched_plain, 256, false, s);
+  HIPC(hipStreamSynchronize(s));
+  P.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+void extract_csr(sable_plan_s& P, const Resid& R, hipStream_t s) {
+  P.csr_nnz = R.nnz;
+  P.csr_ptr.alloc(R.nrows + 1);
+  P.csr_col.alloc(R.nnz);
+  P.csr_val.alloc(R.nnz);
+  HIPC(hipMemcpyAsync(P.csr_ptr.p, R.ptr.p, (R.nrows + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  if (R.nnz) {
+    HIPC(hipMemcpyAsync(P.csr_col.p, R.col.p, R.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPC(hipMemcpyAsync(P.csr_val.p, R.val.p, R.nnz * sizeof(float), hipMemcpyDeviceToDevice, s));
+    k_csr_owner<<<grid_for(R.nnz, 256), 256, 0, s>>>(R.id.p, R.nnz, P.owner.p, P.slot.p);
+    LAUNCH_CHECK();
+  }
+  HIPC(hipStreamSynchronize(s));
+}
+
+}  // namespace sable
+
+sable::i64 sable_plan_s::device_bytes() const {
+  sable::i64 b = 0;
+  b += vdia_val.bytes() + idiag.bytes() + seg_row_start.bytes() + seg_nrows.bytes() +
+       seg_ndiags.bytes() + seg_idiag_ptr.bytes() + seg_val_ptr.bytes();
+  b += blk.bytes() + blk_val_ptr.bytes() + vbr_val.bytes() + vbr_hi.bytes() + vbr_lo.bytes();
+  b += csr_ptr.bytes() + csr_col.bytes() + csr_val.bytes();
+  b += a_ptr.bytes() + a_col.bytes() + a_val.bytes() + owner.bytes() + slot.bytes();
+  for (const sable::Schedule* S : {&sched, &sched_plain})
+    b += S->tile_seg_lo.bytes() + S->tile_seg_hi.bytes() + S->tile_blk_ptr.bytes() +
+         S->tile_blk.bytes();
+  return b;
+}
+
+using namespace sable;
+
+extern "C" {
+
+const char* sable_last_error(void) { return sable::last_error(); }
+
+sable_status sable_thresholds_default(sable_thresholds* out) {
+  if (!out) {
+    set_error("NULL output");
+    return SABLE_ERR_INVALID_ARG;
+  }
+  out->delta_band_pm = 750;
+  out->delta_block_pm = 500;
+  out->amin_band = 2500;
+  out->amin_block = 2500;
+  out->lseg = 64;
+  out->wmax = 32;
+  out->dmax = -1;
+  out->coverage_pm = 80;
+  out->tile_set_mask = 0;
+  out->flags = SABLE_F_SPLIT_BF16;
+  return SABLE_OK;
+}
+
+sable_status sable_plan(const sable_csr* A, const sable_extractor* list, int32_t nlist,
+                        const sable_thresholds* th_in, void* stream, sable_plan_t* out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    if (!A || !list || !out) SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument");
+    if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0)
+      SB_THROW(SABLE_ERR_INVALID_ARG, "negative dimension");
+    if (A->nnz >= (i64)INT32_MAX) SB_THROW(SABLE_ERR_TOO_LARGE, "nnz >= 2^31");
+    if (!A->indptr || (A->nnz > 0 && (!A->indices || !A->values)))
+      SB_THROW(SABLE_ERR_INVALID_ARG, "NULL CSR array");
+    if (nlist < 1 || nlist > 3) SB_THROW(SABLE_ERR_INVALID_ARG, "extractor list length %d", nlist);
+    if (list[nlist - 1].kind != SABLE_X_CSR)
+      SB_THROW(SABLE_ERR_INCOMPLETE, "the extractor list must end with the CSR catch-all");
+    for (int e = 0; e < nlist - 1; ++e) {
+      if (list[e].kind != SABLE_X_VDIA && list[e].kind != SABLE_X_VBR)
+        SB_THROW(SABLE_ERR_INVALID_ARG, "extractor %d: kind %d", e, list[e].kind);
+      for (int f = 0; f < e; ++f)
+        if (list[f].kind == list[e].kind) SB_THROW(SABLE_ERR_INVALID_ARG, "duplicate extractor kind");
+      if (list[e].kind == SABLE_X_VBR) {
+        const int m = list[e].vbr_mode;
+        if (m < 0 || m > 2) SB_THROW(SABLE_ERR_INVALID_ARG, "vbr_mode %d", m);
+        if (m == SABLE_VBR_PAPER && !vbr_paper_fits(A->nrows, A->ncols))
+          SB_THROW(SABLE_ERR_TOO_LARGE, "literal block search over budget for %dx%d", A->nrows,
+                   A->ncols);
+      }
+    }
+    sable_thresholds th;
+    sable_thresholds_default(&th);
+    if (th_in) th = *th_in;
+    if (th.delta_block_pm < 500 || th.delta_block_pm > 1000 || th.delta_band_pm < 1 ||
+        th.delta_band_pm > 1000 || th.amin_block < 1 || th.amin_band < 1 || th.lseg < 1 ||
+        th.wmax < 0 || th.coverage_pm < 0 || th.coverage_pm > 1000 || th.tile_set_mask < 0 ||
+        th.tile_set_mask > 31)
+      SB_THROW(SABLE_ERR_INVALID_ARG, "threshold out of range");
+    hipStream_t s = (hipStream_t)stream;
+    if (!validate_csr_device(*A, s)) SB_THROW(SABLE_ERR_INVALID_CSR, "input is not canonical CSR");
+    sable_plan_s* P = new sable_plan_s();
+    try {
+      build_plan(*P, *A, list, nlist, th, s);
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      delete P;
+      throw;
+    }
+    *out = P;
+  });
+}
+
+sable_status sable_plan_destroy(sable_plan_t p) {
+  return guard([&] {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    delete p;
+  });
+}
+
+sable_status sable_plan_info(sable_plan_t p, sable_plan_stats* o) {
+  return guard([&] {
+    if (!p || !o) SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument");
+    std::memset(o, 0, sizeof(*o));
+    o->nrows = p->nrows;
+    o->ncols = p->ncols;
+    o->nnz = p->nnz;
+    o->nseg = p->nseg;
+    o->nidiag = p->nidiag;
+    o->vdia_cells = p->vdia_cells;
+    o->vdia_nnz = p->vdia_nnz;
+    o->nblk = p->nblk;
+    o->vbr_mode_used = p->vbr_mode_used;
+    o->vbr_tile = p->vbr_tile;
+    o->vbr_cells = p->vbr_cells;
+    o->vbr_nnz = p->vbr_nnz;
+    o->csr_nnz = p->csr_nnz;
+    // compulsory bytes of the formats: VDIA values + per-segment metadata, VBR values,
+    // CSR values + column indices + row pointers
+    o->bytes_matrix = 4 * p->vdia_cells + 20 * (i64)p->nseg + 4 * p->vbr_cells +
+                      8 * p->csr_nnz + 4 * ((i64)p->nrows + 1);
+    o->device_bytes = p->device_bytes();
+    o->plan_ms = p->plan_ms;
+  });
+}
+
+sable_status sable_plan_export(sable_plan_t p, const sable_partition_host* o) {
+  return guard([&] {
+    if (!p || !o) SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument");
+    HIPC(hipDeviceSynchronize());
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+      if (dst && bytes) HIPC(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    };
+    cp(o->vdia_val, p->vdia_val.p, p->vdia_cells * sizeof(float));
+    cp(o->idiag, p->idiag.p, p->nidiag * sizeof(int32_t));
+    cp(o->seg_row_start, p->seg_row_start.p, p->nseg * sizeof(int32_t));
+    cp(o->seg_nrows, p->seg_nrows.p, p->nseg * sizeof(int32_t));
+    cp(o->seg_ndiags, p->seg_ndiags.p, p->nseg * sizeof(int32_t));
+    cp(o->seg_val_ptr, p->seg_val_ptr.p, p->nseg * sizeof(int64_t));
+    cp(o->seg_idiag_ptr, p->seg_idiag_ptr.p, p->nseg * sizeof(int32_t));
+    cp(o->blk, p->blk.p, 4 * (size_t)p->nblk * sizeof(int32_t));
+    cp(o->blk_val_ptr, p->blk_val_ptr.p, p->nblk * sizeof(int64_t));
+    cp(o->vbr_val, p->vbr_val.p, p->vbr_cells * sizeof(float));
+    cp(o->csr_col, p->csr_col.p, p->csr_nnz * sizeof(int32_t));
+    cp(o->csr_val, p->csr_val.p, p->csr_nnz * sizeof(float));
+    cp(o->owner, p->owner.p, p->nnz * sizeof(int8_t));
+    cp(o->slot, p->slot.p, p->nnz * sizeof(int64_t));
+    if (o->csr_ptr) {
+      std::vector<int32_t> h(p->nrows + 1);
+      HIPC(hipMemcpy(h.data(), p->csr_ptr.p, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < h.size(); ++i) o->csr_ptr[i] = h[i];
+    }
+  });
+}
+
+sable_status sable_spmv(sable_plan_t p, const float* x, float* y, void* stream) {
+  return guard([&] {
+    if (!p || (!x && p->ncols) || (!y && p->nrows)) SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument");
+    if (p->nrows == 0) return;
+    launch_spmv(*p, x, y, (hipStream_t)stream);
+  });
+}
+
+sable_status sable_csr_spmv(sable_plan_t p, const float* x, float* y, void* stream) {
+  return guard([&] {
+    if (!p || (!x && p->ncols) || (!y && p->nrows)) SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument");
+    if (p->nrows == 0) return;
+    launch_spmv_plain(*p, x, y, (hipStream_t)stream);
+  });
+}
+
+sable_status sable_spmm(sable_plan_t p, const float* X, float* Y, int32_t n, void* stream) {
+  return guard([&] {
+    if (!p || n < 1 || (!X && p->ncols) || (!Y && p->nrows))
+      SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument or n < 1");
+    if (((uintptr_t)X & 15) || ((uintptr_t)Y & 15))
+      SB_THROW(SABLE_ERR_INVALID_ARG, "X and Y must be 16-byte aligned");
+    if (p->nrows == 0) return;
+    launch_spmm(*p, X, Y, n, (hipStream_t)stream);
+  });
+}
+
+sable_status sable_update_values(sable_plan_t p, const float* values, void* stream) {
+  return guard([&] {
+    if (!p || (!values && p->nnz)) SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->nnz) {
+      k_update_values<<<grid_for(p->nnz, 256), 256, 0, s>>>(values, p->nnz, p->owner.p, p->slot.p,
+                                                            p->vdia_val.p, p->vbr_val.p,
+                                                            p->csr_val.p, p->a_val.p);
+      LAUNCH_CHECK();
+    }
+    if (p->vbr_cells && (p->flags & SABLE_F_SPLIT_BF16)) build_bf16_split(*p, s);
+  });
+}
+
+sable_status sable_error_norm_f64(const float* y, const double* yref, int64_t len, void* stream,
+                                  double* out) {
+  return guard([&] {
+    if (!out || len < 0 || (len > 0 && (!y || !yref))) SB_THROW(SABLE_ERR_INVALID_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = (int)std::min<i64>(1024, std::max<i64>(1, (len + kNormThreads - 1) / kNormThreads));
+    DBuf<double> part(2 * (size_t)nb), res(2);
+    k_norm_partial<<<nb, kNormThreads, 0, s>>>(y, yref, len, part.p);
+    LAUNCH_CHECK();
+    k_norm_final<<<1, 1, 0, s>>>(part.p, nb, res.p);
+    LAUNCH_CHECK();
+    double h[2];
+    HIPC(hipMemcpyAsync(h, res.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    const double num = std::sqrt(h[0]), den = std::sqrt(h[1]);
+    *out = den > 0 ? num / den : num;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,282 @@
+// Executor: tile schedule, fused SpMV / SpMM launches, plain CSR baseline, bf16 split.
+#include <algorithm>
+
+#include "exec.h"
+
+namespace sable {
+
+PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain) {
+  PlanView v;
+  std::memset(&v, 0, sizeof(v));
+  v.nrows = P.nrows;
+  v.ncols = P.ncols;
+  v.rows_per_tile = S.rows_per_tile;
+  v.ntiles = S.ntiles;
+  v.tile_seg_lo = S.tile_seg_lo.p;
+  v.tile_seg_hi = S.tile_seg_hi.p;
+  v.tile_blk_ptr = S.tile_blk_ptr.p;
+  v.tile_blk = S.tile_blk.p;
+  if (plain) {
+    v.csr_ptr = P.a_ptr.p;
+    v.csr_col = P.a_col.p;
+    v.csr_val = P.a_val.p;
+    return v;
+  }
+  v.nseg = P.nseg;
+  v.nblk = P.nblk;
+  v.vdia_val = P.vdia_val.p;
+  v.idiag = P.idiag.p;
+  v.seg_row_start = P.seg_row_start.p;
+  v.seg_nrows = P.seg_nrows.p;
+  v.seg_ndiags = P.seg_ndiags.p;
+  v.seg_val_ptr = P.seg_val_ptr.p;
+  v.seg_idiag_ptr = P.seg_idiag_ptr.p;
+  v.blk = P.blk.p;
+  v.blk_val_ptr = P.blk_val_ptr.p;
+  v.vbr_val = P.vbr_val.p;
+  v.vbr_hi = P.vbr_hi.p;
+  v.vbr_lo = P.vbr_lo.p;
+  v.csr_ptr = P.csr_ptr.p;
+  v.csr_col = P.csr_col.p;
+  v.csr_val = P.csr_val.p;
+  return v;
+}
+
+namespace {
+
+// ---- schedule ----------------------------------------------------------------------------
+
+__global__ void k_tile_segs(const int32_t* __restrict__ srs, const int32_t* __restrict__ snr,
+                            int nseg, int RT, int ntiles, int nrows, int32_t* __restrict__ lo,
+                            int32_t* __restrict__ hi) {
+  for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < ntiles; t += (i64)gridDim.x * blockDim.x) {
+    const int a = (int)(t * RT), b = (int)min((i64)nrows, (t + 1) * RT);
+    int l = 0, h = nseg;  // first segment whose end > a (ends are sorted: segments disjoint)
+    while (l < h) { int m = (l + h) >> 1; if (srs[m] + snr[m] <= a) l = m + 1; else h = m; }
+    lo[t] = l;
+    l = 0; h = nseg;      // first segment starting at or after b
+    while (l < h) { int m = (l + h) >> 1; if (srs[m] < b) l = m + 1; else h = m; }
+    hi[t] = l;
+  }
+}
+
+__global__ void k_blk_tile_counts(const int32_t* __restrict__ blk, int nblk, int RT,
+                                  int32_t* __restrict__ cnt) {
+  for (i64 b = blockIdx.x * (i64)blockDim.x + threadIdx.x; b < nblk; b += (i64)gridDim.x * blockDim.x)
+    cnt[b] = (blk[4 * b + 1] - 1) / RT - blk[4 * b] / RT + 1;
+}
+
+__global__ void k_blk_tile_pairs(const int32_t* __restrict__ blk, const int32_t* __restrict__ off,
+                                 int nblk, int RT, uint64_t* __restrict__ keys,
+                                 int32_t* __restrict__ vals) {
+  for (i64 b = blockIdx.x * (i64)blockDim.x + threadIdx.x; b < nblk; b += (i64)gridDim.x * blockDim.x) {
+    const int t0 = blk[4 * b] / RT, t1 = (blk[4 * b + 1] - 1) / RT;
+    for (int t = t0; t <= t1; ++t) {
+      keys[off[b] + (t - t0)] = ((uint64_t)t << 32) | (uint64_t)b;
+      vals[off[b] + (t - t0)] = (int32_t)b;
+    }
+  }
+}
+
+__global__ void k_tile_ptr(const uint64_t* __restrict__ keys, i64 n, int ntiles,
+                           int32_t* __restrict__ ptr) {
+  for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t <= ntiles; t += (i64)gridDim.x * blockDim.x) {
+    const uint64_t key = (uint64_t)t << 32;
+    i64 l = 0, h = n;
+    while (l < h) { i64 m = (l + h) >> 1; if (keys[m] < key) l = m + 1; else h = m; }
+    ptr[t] = (int32_t)l;
+  }
+}
+
+__global__ void k_zero_i32(int32_t* __restrict__ a, i64 n) {
+  for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x) a[k] = 0;
+}
+
+// ---- bf16 split (round to nearest even) -----------------------------------------------------
+
+__device__ inline uint16_t to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ void k_split(const float* __restrict__ a, i64 n, uint16_t* __restrict__ hi,
+                        uint16_t* __restrict__ lo) {
+  for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x) {
+    const float v = a[k];
+    const uint16_t h = to_bf16_rne(v);
+    hi[k] = h;
+    lo[k] = to_bf16_rne(v - __uint_as_float((uint32_t)h << 16));
+  }
+}
+
+// ---- products ---------------------------------------------------------------------------------
+
+template <int W>
+__global__ __launch_bounds__(256) void k_spmv_fused(PlanView P, const float* __restrict__ x,
+                                                   float* __restrict__ y) {
+  __shared__ float part[256];
+  spmv_tile<W>(P, blockIdx.x, x, y, part);
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_spmv_plain(const int32_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const float* __restrict__ val, int nrows,
+                                                   const float* __restrict__ x, float* __restrict__ y) {
+  const int rows_per_block = 256 / W;
+  csr_rows<W>(ptr, col, val, nrows, x, y, blockIdx.x * rows_per_block, rows_per_block);
+}
+
+// Fused SpMM (VALU): one wave per row, lanes across 64-column chunks of X / Y.
+__global__ __launch_bounds__(256) void k_spmm_fused_valu(PlanView P, const float* __restrict__ X,
+                                                        float* __restrict__ Y, int n) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + wave;
+  if (r >= P.nrows) return;
+  // band segment containing r
+  int s = -1;
+  {
+    int lo = 0, hi = P.nseg - 1;
+    while (lo <= hi) {
+      int m = (lo + hi) >> 1;
+      if (P.seg_row_start[m] <= r) { s = m; lo = m + 1; } else hi = m - 1;
+    }
+    if (s >= 0 && r >= P.seg_row_start[s] + P.seg_nrows[s]) s = -1;
+  }
+  const int tile = r / P.rows_per_tile;
+  for (int cb = 0; cb < n; cb += 64) {
+    const int c = cb + lane;
+    const bool ok = c < n;
+    float acc = 0.f;
+    if (s >= 0) {
+      const int rs = P.seg_row_start[s], nr = P.seg_nrows[s], nd = P.seg_ndiags[s];
+      const int32_t* od = P.idiag + P.seg_idiag_ptr[s];
+      const float* v = P.vdia_val + P.seg_val_ptr[s] + (r - rs);
+      for (int t = 0; t < nd; ++t) {
+        const int col = r + od[t];
+        if ((unsigned)col < (unsigned)P.ncols && ok) acc += v[(i64)t * nr] * X[(i64)col * n + c];
+      }
+    }
+    for (int q = P.tile_blk_ptr[tile]; q < P.tile_blk_ptr[tile + 1]; ++q) {
+      const int b = P.tile_blk[q];
+      const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
+      if (r < br0 || r >= br1) continue;
+      const int c0 = P.blk[4 * b + 2], c1 = P.blk[4 * b + 3], h = br1 - br0;
+      const float* v = P.vbr_val + P.blk_val_ptr[b] + (r - br0);
+      if (ok)
+        for (int cc = c0; cc < c1; ++cc) acc += v[(i64)(cc - c0) * h] * X[(i64)cc * n + c];
+    }
+    float cs = 0.f;
+    if (ok)
+      for (int k = P.csr_ptr[r]; k < P.csr_ptr[r + 1]; ++k) cs += P.csr_val[k] * X[(i64)P.csr_col[k] * n + c];
+    if (ok) Y[(i64)r * n + c] = acc + cs;
+  }
+}
+
+}  // namespace
+
+void build_schedule(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStream_t s) {
+  S.rows_per_tile = RT;
+  S.ntiles = (P.nrows + RT - 1) / RT;
+  const int nt = S.ntiles;
+  S.tile_seg_lo.alloc(nt);
+  S.tile_seg_hi.alloc(nt);
+  S.tile_blk_ptr.alloc(nt + 1);
+  const int nseg = with_formats ? P.nseg : 0;
+  const int nblk = with_formats ? P.nblk : 0;
+  if (nt) {
+    if (nseg) {
+      k_tile_segs<<<grid_for(nt, 256), 256, 0, s>>>(P.seg_row_start.p, P.seg_nrows.p, nseg, RT, nt,
+                                                    P.nrows, S.tile_seg_lo.p, S.tile_seg_hi.p);
+    } else {
+      k_zero_i32<<<grid_for(nt, 256), 256, 0, s>>>(S.tile_seg_lo.p, nt);
+      LAUNCH_CHECK();
+      k_zero_i32<<<grid_for(nt, 256), 256, 0, s>>>(S.tile_seg_hi.p, nt);
+    }
+    LAUNCH_CHECK();
+  }
+  if (!nblk) {
+    S.tile_blk.alloc(1);
+    k_zero_i32<<<grid_for(nt + 1, 256), 256, 0, s>>>(S.tile_blk_ptr.p, nt + 1);
+    LAUNCH_CHECK();
+    HIPC(hipStreamSynchronize(s));
+    return;
+  }
+  DBuf<int32_t> cnt(nblk), off(nblk + 1);
+  k_blk_tile_counts<<<grid_for(nblk, 256), 256, 0, s>>>(P.blk.p, nblk, RT, cnt.p);
+  LAUNCH_CHECK();
+  exclusive_scan_i32(cnt.p, off.p, nblk, s);
+  int32_t npairs = 0;
+  HIPC(hipMemcpyAsync(&npairs, off.p + nblk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  DBuf<uint64_t> keys(npairs);
+  DBuf<int32_t> vals(npairs);
+  k_blk_tile_pairs<<<grid_for(nblk, 256), 256, 0, s>>>(P.blk.p, off.p, nblk, RT, keys.p, vals.p);
+  LAUNCH_CHECK();
+  sort_pairs_u64(keys, vals, npairs, 32 + bits_for((uint64_t)nt), s);
+  k_tile_ptr<<<grid_for(nt + 1, 256), 256, 0, s>>>(keys.p, npairs, nt, S.tile_blk_ptr.p);
+  LAUNCH_CHECK();
+  HIPC(hipStreamSynchronize(s));
+  S.tile_blk = std::move(vals);
+}
+
+void build_bf16_split(sable_plan_s& P, hipStream_t s) {
+  if (P.vbr_hi.n != (size_t)P.vbr_cells) {
+    P.vbr_hi.alloc(P.vbr_cells);
+    P.vbr_lo.alloc(P.vbr_cells);
+  }
+  if (P.vbr_cells) {
+    k_split<<<grid_for(P.vbr_cells, 256), 256, 0, s>>>(P.vbr_val.p, P.vbr_cells, P.vbr_hi.p, P.vbr_lo.p);
+    LAUNCH_CHECK();
+  }
+}
+
+static int csr_width(double avg) {
+  if (avg <= 2) return 1;
+  if (avg <= 6) return 4;
+  if (avg <= 12) return 8;
+  return 16;
+}
+
+void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
+  const PlanView v = make_view(P, P.sched, false);
+  const int W = P.prm.spmv_csr_width > 0 ? P.prm.spmv_csr_width
+                                         : csr_width(P.nrows ? (double)P.csr_nnz / P.nrows : 0);
+  const unsigned nb = (unsigned)v.ntiles;
+  switch (W) {
+    case 1: k_spmv_fused<1><<<nb, 256, 0, s>>>(v, x, y); break;
+    case 2: k_spmv_fused<2><<<nb, 256, 0, s>>>(v, x, y); break;
+    case 4: k_spmv_fused<4><<<nb, 256, 0, s>>>(v, x, y); break;
+    case 8: k_spmv_fused<8><<<nb, 256, 0, s>>>(v, x, y); break;
+    default: k_spmv_fused<16><<<nb, 256, 0, s>>>(v, x, y); break;
+  }
+  LAUNCH_CHECK();
+}
+
+void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
+  const int W = P.prm.plain_csr_width > 0 ? P.prm.plain_csr_width
+                                          : csr_width(P.nrows ? (double)P.nnz / P.nrows : 0);
+  const int rpb = 256 / W;
+  const unsigned nb = (unsigned)((P.nrows + rpb - 1) / rpb);
+  switch (W) {
+    case 1: k_spmv_plain<1><<<nb, 256, 0, s>>>(P.a_ptr.p, P.a_col.p, P.a_val.p, P.nrows, x, y); break;
+    case 2: k_spmv_plain<2><<<nb, 256, 0, s>>>(P.a_ptr.p, P.a_col.p, P.a_val.p, P.nrows, x, y); break;
+    case 4: k_spmv_plain<4><<<nb, 256, 0, s>>>(P.a_ptr.p, P.a_col.p, P.a_val.p, P.nrows, x, y); break;
+    case 8: k_spmv_plain<8><<<nb, 256, 0, s>>>(P.a_ptr.p, P.a_col.p, P.a_val.p, P.nrows, x, y); break;
+    case 16: k_spmv_plain<16><<<nb, 256, 0, s>>>(P.a_ptr.p, P.a_col.p, P.a_val.p, P.nrows, x, y); break;
+    case 32: k_spmv_plain<32><<<nb, 256, 0, s>>>(P.a_ptr.p, P.a_col.p, P.a_val.p, P.nrows, x, y); break;
+    default: k_spmv_plain<64><<<nb, 256, 0, s>>>(P.a_ptr.p, P.a_col.p, P.a_val.p, P.nrows, x, y); break;
+  }
+  LAUNCH_CHECK();
+}
+
+void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s) {
+  const PlanView v = make_view(P, P.sched, false);
+  const unsigned nb = (unsigned)((P.nrows + 3) / 4);
+  k_spmm_fused_valu<<<nb, 256, 0, s>>>(v, X, Y, n);
+  LAUNCH_CHECK();
+}
+
+}  // namespace sable

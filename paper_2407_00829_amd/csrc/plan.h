@@ -1,0 +1,101 @@
+// Internal plan representation: formats in HBM plus the execution schedule.
+#pragma once
+
+#include "common.h"
+
+namespace sable {
+
+// Residual matrix on the device: CSR (int32 row pointers, nnz < 2^31) plus, per stored
+// entry, its index in the input matrix (to build the owner/slot map and refresh values).
+struct Resid {
+  int nrows = 0, ncols = 0;
+  i64 nnz = 0;
+  DBuf<int32_t> ptr, col, id;
+  DBuf<float> val;
+};
+
+struct SegRec {  // band segment produced by the band extractor: rows [i0, j), [d-L, d+U]
+  int32_t i0, j, L, U, d, cand;
+  i64 z;
+};
+
+struct BlkRec {  // block rectangle rows [r0, r1), columns [c0, c1)
+  int32_t r0, r1, c0, c1;
+};
+
+// Launch parameters of the fused kernels (autotuned).
+struct ExecParams {
+  int spmv_rows_per_tile = 256;  // rows per workgroup tile of the fused SpMV
+  int spmv_csr_width = 0;        // lanes per CSR row in the fused SpMV (0: from row length)
+  int plain_csr_width = 0;       // lanes per row of the plain CSR baseline (0: from row length)
+  int spmm_mode = 0;             // fused SpMM variant
+};
+
+struct Schedule {
+  int rows_per_tile = 0;
+  int ntiles = 0;
+  DBuf<int32_t> tile_seg_lo, tile_seg_hi;  // VDIA segments overlapping each tile
+  DBuf<int32_t> tile_blk_ptr, tile_blk;    // VBR blocks overlapping each tile
+};
+
+}  // namespace sable
+
+struct sable_plan_s {
+  int nrows = 0, ncols = 0;
+  sable::i64 nnz = 0;
+  // VDIA (Sec. 4.2.1)
+  int nseg = 0;
+  sable::i64 nidiag = 0, vdia_cells = 0, vdia_nnz = 0;
+  sable::DBuf<float> vdia_val;
+  sable::DBuf<int32_t> idiag, seg_row_start, seg_nrows, seg_ndiags, seg_idiag_ptr;
+  sable::DBuf<sable::i64> seg_val_ptr;
+  // VBR (App. B): blk = (r0, r1, c0, c1) per block, values column-major per block
+  int nblk = 0;
+  int vbr_mode_used = 0, vbr_tile = 0;
+  sable::i64 vbr_cells = 0, vbr_nnz = 0;
+  sable::DBuf<int32_t> blk;
+  sable::DBuf<sable::i64> blk_val_ptr;
+  sable::DBuf<float> vbr_val;
+  sable::DBuf<uint16_t> vbr_hi, vbr_lo;  // bf16 split copies (same layout as vbr_val)
+  // CSR remainder
+  sable::i64 csr_nnz = 0;
+  sable::DBuf<int32_t> csr_ptr, csr_col;
+  sable::DBuf<float> csr_val;
+  // Whole input as CSR (plain baseline) and owner/slot map of every input entry
+  sable::DBuf<int32_t> a_ptr, a_col;
+  sable::DBuf<float> a_val;
+  sable::DBuf<int8_t> owner;
+  sable::DBuf<sable::i64> slot;
+  // schedule and tuned parameters
+  sable::Schedule sched;
+  sable::Schedule sched_plain;
+  sable::ExecParams prm;
+  uint32_t flags = 0;
+  double plan_ms = 0.0;
+  sable::i64 device_bytes() const;
+};
+
+namespace sable {
+
+// Extractors (each claims entries of R, fills its part of the plan, marks claimed[k]).
+void extract_bands(sable_plan_s& P, const Resid& R, const sable_thresholds& th,
+                   DBuf<uint8_t>& claimed, hipStream_t s);
+void extract_blocks(sable_plan_s& P, const Resid& R, const sable_thresholds& th, int mode,
+                    DBuf<uint8_t>& claimed, hipStream_t s);
+void extract_csr(sable_plan_s& P, const Resid& R, hipStream_t s);
+
+// Residual management.
+void resid_from_input(Resid& R, const sable_csr& A, hipStream_t s);
+void resid_compact(Resid& R, const DBuf<uint8_t>& claimed, hipStream_t s);
+void entry_rows(const Resid& R, DBuf<int32_t>& rows, hipStream_t s);
+bool validate_csr_device(const sable_csr& A, hipStream_t s);
+
+// Schedules and kernels.
+void build_schedule(sable_plan_s& P, Schedule& S, int rows_per_tile, bool with_formats,
+                    hipStream_t s);
+void build_bf16_split(sable_plan_s& P, hipStream_t s);
+void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
+void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
+void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s);
+
+}  // namespace sable

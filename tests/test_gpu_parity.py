@@ -1,0 +1,199 @@
+"""GPU parity: libsable (through its C ABI) against the CPU oracle.
+
+* the partition export is bit-exact: every VDIA / VBR / CSR array, the owner/slot map;
+* SpMV results within normwise relative error 1e-5 of the FP64 oracle, SpMM with split-bf16
+  blocks within 1e-4, every result reports its error;
+* results are bitwise reproducible run to run.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_00829_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2407_00829_amd import sable  # noqa: E402
+
+V, B, C = oracle.VDIA, oracle.VBR, oracle.CSR
+KIND = {V: sable.SABLE_X_VDIA, B: sable.SABLE_X_VBR, C: sable.SABLE_X_CSR}
+EXPORT_KEYS = ("vdia_val", "idiag", "seg_row_start", "seg_nrows", "seg_ndiags", "seg_val_ptr",
+               "seg_idiag_ptr", "blk", "blk_val_ptr", "vbr_val", "csr_ptr", "csr_col", "csr_val",
+               "owner", "slot")
+
+
+def to_sable_th(th: oracle.Thresholds) -> sable.Thresholds:
+    return sable.Thresholds(th.delta_band_pm, th.delta_block_pm, th.amin_band, th.amin_block,
+                            th.lseg, th.wmax, th.dmax, th.coverage_pm, th.tile_set_mask)
+
+
+def gpu_plan(A, kinds, mode, th):
+    print(f"[plan] {A.nrows}x{A.ncols} nnz={A.nnz} kinds={kinds} mode={mode}", flush=True)
+    return sable.plan_host(A, [KIND[k] for k in kinds], mode, to_sable_th(th))
+
+
+def assert_same_partition(got, ref):
+    for k in EXPORT_KEYS:
+        a, b = np.asarray(got[k]), np.asarray(ref[k])
+        assert a.shape == b.shape, (k, a.shape, b.shape)
+        if a.dtype == np.float32:
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), k
+        else:
+            assert np.array_equal(a, b), k
+    if ref["vbr_mode"]:
+        assert got["vbr_mode"] == ref["vbr_mode"]
+        assert got["vbr_tile"] == ref["vbr_tile"]
+
+
+def run_spmv(p, A, x):
+    xd = torch.from_numpy(x).cuda()
+    y = torch.full((A.nrows,), float("nan"), device="cuda")
+    sable.sable_spmv(p, xd, y)
+    torch.cuda.synchronize()
+    return y
+
+
+def check_spmv(p, A, x, tol=1e-5):
+    y = run_spmv(p, A, x)
+    ref = oracle.spmv(A, x)
+    err = oracle.rel_err(y.cpu().numpy(), ref)
+    # the GPU FP64 error-norm reduction reports the same number
+    gerr = sable.sable_error_norm_f64(y, torch.from_numpy(ref).cuda())
+    print(f"  spmv rel_err={err:.3e} (gpu norm {gerr:.3e})", flush=True)
+    assert err <= tol
+    assert abs(gerr - err) <= 1e-9 + 1e-6 * err
+    y2 = run_spmv(p, A, x)
+    assert torch.equal(y, y2), "SpMV not bitwise reproducible"
+    return err
+
+
+def check_spmm(p, A, n, seed=0, tol=1e-4):
+    X = synth.gen_dense_matrix(seed, A.ncols, n)
+    Xd = torch.from_numpy(X).cuda()
+    Y = torch.full((A.nrows, n), float("nan"), device="cuda")
+    sable.sable_spmm(p, Xd, Y, n)
+    torch.cuda.synchronize()
+    ref = oracle.spmm(A, X)
+    err = oracle.rel_err(Y.cpu().numpy(), ref)
+    print(f"  spmm n={n} rel_err={err:.3e}", flush=True)
+    assert err <= tol
+    Y2 = torch.empty_like(Y)
+    sable.sable_spmm(p, Xd, Y2, n)
+    torch.cuda.synchronize()
+    assert torch.equal(Y, Y2), "SpMM not bitwise reproducible"
+    return err
+
+
+# ---- worked example ---------------------------------------------------------------------
+
+def test_fig_vdia_on_gpu():
+    D = np.zeros((10, 10), np.float32)
+    D[1, 0:3] = [4, 7, 2]; D[2, 1:4] = [1, 5, 3]; D[3, 2:5] = [2, 8, 1]; D[4, 3:6] = [3, 6, 4]
+    D[6, 0:4] = [3, 2, 5, 1]; D[7, 1:5] = [4, 3, 7, 2]; D[8, 2:6] = [1, 6, 2, 8]
+    r, c = np.nonzero(D)
+    A = synth.from_coo(10, 10, r, c, D[r, c])
+    th = oracle.Thresholds(lseg=3, amin_band=12)
+    p = gpu_plan(A, [V, C], 0, th)
+    got = sable.sable_plan_export(p)
+    assert got["vdia_val"].tolist() == [4, 1, 2, 3, 7, 5, 8, 6, 2, 3, 1, 4, 3, 4, 1, 2, 3, 6, 5, 7, 2, 1, 2, 8]
+    assert got["idiag"].tolist() == [-1, 0, 1, -6, -5, -4, -3]
+    assert_same_partition(got, oracle.plan(A, [V, C], 0, th))
+    check_spmv(p, A, np.arange(10, dtype=np.float32))
+
+
+# ---- random small matrices: every plan shape, both block-search modes ---------------------
+
+PLANS = [[C], [V, C], [B, C], [V, B, C], [B, V, C]]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small_bit_exact(seed):
+    rng = np.random.default_rng(100 + seed)
+    nr, nc = int(rng.integers(40, 300)), int(rng.integers(40, 300))
+    A = synth.gen_random_small(seed, nr, nc, 0.03, nbands=4, nblocks=4, block_max=40)
+    th = oracle.Thresholds(lseg=8, amin_band=32, amin_block=64, coverage_pm=40 * (seed % 3),
+                           delta_band_pm=[500, 700, 900][seed % 3],
+                           delta_block_pm=[500, 700, 900][(seed + 1) % 3])
+    x = synth.gen_dense_vector(seed, A.ncols)
+    for kinds in PLANS:
+        for mode in (oracle.MODE_PAPER, oracle.MODE_TILED):
+            if B not in kinds and mode == oracle.MODE_TILED:
+                continue
+            p = gpu_plan(A, kinds, mode, th)
+            assert_same_partition(sable.sable_plan_export(p), oracle.plan(A, kinds, mode, th))
+            check_spmv(p, A, x)
+            check_spmm(p, A, 5 + seed)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_c1_small_paper_mode_bit_exact(seed):
+    """C1-style structure at n = 1024 (bands, 12 block-aligned blocks, 0.05% scatter)."""
+    A, x = synth.gen_c1(seed, n=1024)
+    th = oracle.Thresholds(amin_band=256, amin_block=256)
+    kinds = [V, B, C]
+    p = gpu_plan(A, kinds, oracle.MODE_PAPER, th)
+    assert_same_partition(sable.sable_plan_export(p), oracle.plan(A, kinds, oracle.MODE_PAPER, th))
+    check_spmv(p, A, x)
+    check_spmm(p, A, 16)
+
+
+def test_c1_full_tiled_bit_exact():
+    A, x = synth.gen_c1(0)
+    th = oracle.Thresholds(amin_band=256, amin_block=256)
+    for kinds in ([V, B, C], [B, V, C]):
+        p = gpu_plan(A, kinds, oracle.MODE_TILED, th)
+        assert_same_partition(sable.sable_plan_export(p), oracle.plan(A, kinds, oracle.MODE_TILED, th))
+        check_spmv(p, A, x)
+
+
+# ---- edge cases ------------------------------------------------------------------------------
+
+def test_empty_and_degenerate():
+    th = oracle.Thresholds(lseg=2, amin_band=2, amin_block=4)
+    for (nr, nc, dens) in [(1, 1, 1.0), (1, 50, 0.5), (50, 1, 0.5), (300, 7, 0.0), (257, 513, 0.01)]:
+        A = synth.gen_random_small(nr * 7 + nc, nr, nc, dens)
+        x = synth.gen_dense_vector(1, nc)
+        for kinds in PLANS:
+            p = gpu_plan(A, kinds, oracle.MODE_PAPER, th)
+            assert_same_partition(sable.sable_plan_export(p), oracle.plan(A, kinds, 1, th))
+            y = run_spmv(p, A, x)
+            assert np.allclose(y.cpu().numpy(), oracle.spmv(A, x), rtol=1e-5, atol=1e-6)
+
+
+def test_invalid_csr_rejected():
+    A = synth.from_coo(4, 4, [0, 1], [0, 1], [1.0, 2.0])
+    ip, ix, vv = sable.device_csr(A)
+    ix[1] = 7  # column out of range
+    with pytest.raises(sable.SableError) as e:
+        sable.sable_plan(4, 4, ip, ix, vv, [sable.SABLE_X_CSR])
+    assert e.value.code == 2
+
+
+def test_update_values_matches_replan():
+    A, x = synth.gen_c1(1, n=768)
+    th = oracle.Thresholds(amin_band=256, amin_block=256)
+    kinds = [V, B, C]
+    p = gpu_plan(A, kinds, oracle.MODE_PAPER, th)
+    A2 = synth.CSR(A.nrows, A.ncols, A.indptr, A.indices,
+                   synth.gen_dense_vector(9, A.nnz, normal=True))
+    p.nnz = A2.nnz
+    sable.sable_update_values(p, torch.from_numpy(A2.values).cuda())
+    torch.cuda.synchronize()
+    q = gpu_plan(A2, kinds, oracle.MODE_PAPER, th)
+    assert_same_partition(sable.sable_plan_export(p), sable.sable_plan_export(q))
+    y1, y2 = run_spmv(p, A2, x), run_spmv(q, A2, x)
+    assert torch.equal(y1, y2)
+
+
+def test_plain_csr_baseline():
+    A, x = synth.gen_c1(2, n=2048)
+    p = gpu_plan(A, [C], 0, oracle.Thresholds())
+    xd = torch.from_numpy(x).cuda()
+    y = torch.empty(A.nrows, device="cuda")
+    sable.sable_csr_spmv(p, xd, y)
+    torch.cuda.synchronize()
+    assert oracle.rel_err(y.cpu().numpy(), oracle.spmv(A, x)) <= 1e-5
