@@ -198,6 +198,14 @@ sable_status sable_update_values(sable_plan_t p, const float* values, void* stre
 sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, const float* x, float* y,
                             void* stream);
 
+/* Select a fused-kernel variant explicitly (the set sable_autotune chooses from).
+ * op 0 = hybrid SpMV: 0..2 streamed tiles of 256/512/1024 rows, 3..7 row-per-lane with
+ *        1/2/4/8/16 lanes per CSR row;
+ * op 1 = SpMM: 0 tiled with matrix-core blocks, 1 tiled fp32, 2 one wave per row;
+ * op 2 = plain CSR baseline: 0..2 streamed, 3..9 with 1..64 lanes per row.
+ * Every variant computes the same product; each is bitwise reproducible on its own. */
+sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32_t variant);
+
 /* ---- Learned planner (matrix features -> MLP -> extractor list and delta) ------------- */
 #define SABLE_NFEAT 140
 #define SABLE_NCLASS 15

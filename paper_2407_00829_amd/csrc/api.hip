@@ -121,8 +121,10 @@ void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list
     resid_compact(R, claimed, s);
   }
   if (P.vbr_cells && (P.flags & SABLE_F_SPLIT_BF16)) build_bf16_split(P, s);
-  build_schedule(P, P.sched, P.prm.spmv_rows_per_tile, true, s);
-  build_schedule(P, P.sched_plain, 256, false, s);
+  for (int k = 0; k < 3; ++k) {
+    build_schedule(P, P.sched[k], 256 << k, true, s);
+    build_schedule(P, P.sched_plain[k], 256 << k, false, s);
+  }
   HIPC(hipStreamSynchronize(s));
   P.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -153,9 +155,11 @@ sable::i64 sable_plan_s::device_bytes() const {
   b += blk.bytes() + blk_val_ptr.bytes() + vbr_val.bytes() + vbr_hi.bytes() + vbr_lo.bytes();
   b += csr_ptr.bytes() + csr_col.bytes() + csr_val.bytes();
   b += a_ptr.bytes() + a_col.bytes() + a_val.bytes() + owner.bytes() + slot.bytes();
-  for (const sable::Schedule* S : {&sched, &sched_plain})
+  for (int k = 0; k < 6; ++k) {
+    const sable::Schedule* S = k < 3 ? &sched[k] : &sched_plain[k - 3];
     b += S->tile_seg_lo.bytes() + S->tile_seg_hi.bytes() + S->tile_blk_ptr.bytes() +
          S->tile_blk.bytes();
+  }
   return b;
 }
 

@@ -97,6 +97,148 @@ __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const flo
   }
 }
 
+// ---- SpMV tile body, streamed variant ---------------------------------------------------
+// Tile = 256*RPT rows, 256 threads; thread t owns rows r0 + t + 256*q (q < RPT).
+//  1. bands: lane per row, diagonals unrolled by 4 (independent value and x loads);
+//  2. blocks: each block's rows in the tile x column slices are spread over all threads;
+//     slice partials meet in LDS and are added per row in slice order;
+//  3. CSR: the tile's entries are contiguous, so they are read in coalesced chunks, each
+//     thread multiplies entries by gathered x values into LDS, then every row adds its own
+//     products in index order.
+// Per row: y = (bands + blocks) + CSR, in a fixed order (bitwise reproducible).
+constexpr int kSpmvThreads = 256;
+constexpr int kCsrChunk = 4096;
+
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+  // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of tiles so
+  // neighbouring rows (and their x entries) share one L2
+  const int per = (ntiles + 7) >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+template <int RPT>
+__device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
+                                                 const float* __restrict__ x,
+                                                 float* __restrict__ y, float* __restrict__ lds) {
+  constexpr int RT = kSpmvThreads * RPT;
+  float* prod = lds;                 // kCsrChunk products
+  float* part = lds + kCsrChunk;     // RT block partials
+  const int r0 = tile * RT;
+  const int t = threadIdx.x;
+  const int rend = min(r0 + RT, P.nrows);
+  float acc[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) acc[q] = 0.f;
+  // 1. band segments
+  const int slo = P.tile_seg_lo[tile], shi = P.tile_seg_hi[tile];
+  for (int s = slo; s < shi; ++s) {
+    const int rs = P.seg_row_start[s], nr = P.seg_nrows[s], nd = P.seg_ndiags[s];
+    const int32_t* od = P.idiag + P.seg_idiag_ptr[s];
+    const float* vb = P.vdia_val + P.seg_val_ptr[s];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = r0 + t + kSpmvThreads * q;
+      if (r < rs || r >= rs + nr || r >= rend) continue;
+      const float* v = vb + (r - rs);
+      int d = 0;
+      for (; d + 4 <= nd; d += 4) {
+        const int c0 = r + od[d], c1 = r + od[d + 1], c2 = r + od[d + 2], c3 = r + od[d + 3];
+        const float v0 = v[(i64)d * nr], v1 = v[(i64)(d + 1) * nr], v2 = v[(i64)(d + 2) * nr],
+                    v3 = v[(i64)(d + 3) * nr];
+        const float x0 = (unsigned)c0 < (unsigned)P.ncols ? x[c0] : 0.f;
+        const float x1 = (unsigned)c1 < (unsigned)P.ncols ? x[c1] : 0.f;
+        const float x2 = (unsigned)c2 < (unsigned)P.ncols ? x[c2] : 0.f;
+        const float x3 = (unsigned)c3 < (unsigned)P.ncols ? x[c3] : 0.f;
+        acc[q] += v0 * x0;
+        acc[q] += v1 * x1;
+        acc[q] += v2 * x2;
+        acc[q] += v3 * x3;
+      }
+      for (; d < nd; ++d) {
+        const int c = r + od[d];
+        if ((unsigned)c < (unsigned)P.ncols) acc[q] += v[(i64)d * nr] * x[c];
+      }
+    }
+  }
+  // 2. blocks
+  const int blo = P.tile_blk_ptr[tile], bhi = P.tile_blk_ptr[tile + 1];
+  for (int qb = blo; qb < bhi; ++qb) {
+    const int b = P.tile_blk[qb];
+    const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
+    const int c0 = P.blk[4 * b + 2], c1 = P.blk[4 * b + 3];
+    const int h = br1 - br0, w = c1 - c0;
+    const int lo = max(br0, r0), hi = min(br1, rend);
+    const int nrb = hi - lo;
+    if (nrb <= 0) continue;
+    const int S = nrb >= kSpmvThreads ? 1 : kSpmvThreads / nrb;
+    const int cw = (w + S - 1) / S;
+    const float* vb = P.vbr_val + P.blk_val_ptr[b];
+    __syncthreads();
+    for (int i = t; i < nrb * S; i += kSpmvThreads) {
+      const int rl = i % nrb, sl = i / nrb;
+      const int row = lo + rl;
+      const int cb = c0 + sl * cw, ce = min(c1, cb + cw);
+      const float* v = vb + (row - br0);
+      float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+      int c = cb;
+      for (; c + 4 <= ce; c += 4) {
+        p0 += v[(i64)(c - c0) * h] * x[c];
+        p1 += v[(i64)(c + 1 - c0) * h] * x[c + 1];
+        p2 += v[(i64)(c + 2 - c0) * h] * x[c + 2];
+        p3 += v[(i64)(c + 3 - c0) * h] * x[c + 3];
+      }
+      for (; c < ce; ++c) p0 += v[(i64)(c - c0) * h] * x[c];
+      part[i] = (p0 + p1) + (p2 + p3);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = r0 + t + kSpmvThreads * q;
+      if (r < lo || r >= hi) continue;
+      float sacc = 0.f;
+      for (int sl = 0; sl < S; ++sl) sacc += part[sl * nrb + (r - lo)];
+      acc[q] += sacc;
+    }
+  }
+  // 3. CSR entries of the tile, streamed through LDS
+  float cs[RPT];
+  int kb[RPT], ke[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = r0 + t + kSpmvThreads * q;
+    cs[q] = 0.f;
+    kb[q] = r < rend ? P.csr_ptr[r] : 0;
+    ke[q] = r < rend ? P.csr_ptr[r + 1] : 0;
+  }
+  const int e_begin = P.csr_ptr[r0], e_end = P.csr_ptr[rend];
+  for (int e0 = e_begin; e0 < e_end; e0 += kCsrChunk) {
+    const int n = min(kCsrChunk, e_end - e0);
+    __syncthreads();
+    int i = t;
+    for (; i + 3 * kSpmvThreads < n; i += 4 * kSpmvThreads) {
+      const int k0 = e0 + i, k1 = k0 + kSpmvThreads, k2 = k1 + kSpmvThreads, k3 = k2 + kSpmvThreads;
+      const int j0 = P.csr_col[k0], j1 = P.csr_col[k1], j2 = P.csr_col[k2], j3 = P.csr_col[k3];
+      const float a0 = P.csr_val[k0], a1 = P.csr_val[k1], a2 = P.csr_val[k2], a3 = P.csr_val[k3];
+      prod[i] = a0 * x[j0];
+      prod[i + kSpmvThreads] = a1 * x[j1];
+      prod[i + 2 * kSpmvThreads] = a2 * x[j2];
+      prod[i + 3 * kSpmvThreads] = a3 * x[j3];
+    }
+    for (; i < n; i += kSpmvThreads) prod[i] = P.csr_val[e0 + i] * x[P.csr_col[e0 + i]];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int a = max(kb[q], e0), b = min(ke[q], e0 + n);
+      for (int k = a; k < b; ++k) cs[q] += prod[k - e0];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = r0 + t + kSpmvThreads * q;
+    if (r < rend) y[r] = acc[q] + cs[q];
+  }
+}
+
 // Plain CSR SpMV body: W lanes per row over the whole matrix (the baseline family).
 template <int W>
 __device__ __forceinline__ void csr_rows(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,

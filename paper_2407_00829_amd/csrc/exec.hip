@@ -2,6 +2,7 @@
 #include <algorithm>
 
 #include "exec.h"
+#include "spmm_tile.h"
 
 namespace sable {
 
@@ -120,6 +121,15 @@ __global__ __launch_bounds__(256) void k_spmv_fused(PlanView P, const float* __r
   spmv_tile<W>(P, blockIdx.x, x, y, part);
 }
 
+template <int RPT>
+__global__ __launch_bounds__(256) void k_spmv_stream(PlanView P, const float* __restrict__ x,
+                                                    float* __restrict__ y) {
+  __shared__ float lds[kCsrChunk + kSpmvThreads * RPT];
+  const int tile = xcd_tile(blockIdx.x, P.ntiles);
+  if (tile >= P.ntiles) return;
+  spmv_tile_stream<RPT>(P, tile, x, y, lds);
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void k_spmv_plain(const int32_t* __restrict__ ptr,
                                                    const int32_t* __restrict__ col,
@@ -127,6 +137,15 @@ __global__ __launch_bounds__(256) void k_spmv_plain(const int32_t* __restrict__ 
                                                    const float* __restrict__ x, float* __restrict__ y) {
   const int rows_per_block = 256 / W;
   csr_rows<W>(ptr, col, val, nrows, x, y, blockIdx.x * rows_per_block, rows_per_block);
+}
+
+__global__ __launch_bounds__(kMmThreads) void k_spmm_tile(PlanView P, const float* __restrict__ X,
+                                                         float* __restrict__ Y, int n, int use_mfma) {
+  __shared__ float ys[kMmRows * kMmCols];
+  const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
+  const int t = xcd_tile(blockIdx.x, ntile);
+  if (t >= ntile) return;
+  spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, use_mfma != 0);
 }
 
 // Fused SpMM (VALU): one wave per row, lanes across 64-column chunks of X / Y.
@@ -233,31 +252,41 @@ void build_bf16_split(sable_plan_s& P, hipStream_t s) {
   }
 }
 
-static int csr_width(double avg) {
-  if (avg <= 2) return 1;
-  if (avg <= 6) return 4;
-  if (avg <= 12) return 8;
-  return 16;
+static void launch_stream(const PlanView& v, int rpt, const float* x, float* y, hipStream_t s) {
+  const unsigned nb = (unsigned)(((v.ntiles + 7) / 8) * 8);
+  switch (rpt) {
+    case 1: k_spmv_stream<1><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+    case 2: k_spmv_stream<2><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+    default: k_spmv_stream<4><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+  }
+  LAUNCH_CHECK();
 }
 
 void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
-  const PlanView v = make_view(P, P.sched, false);
-  const int W = P.prm.spmv_csr_width > 0 ? P.prm.spmv_csr_width
-                                         : csr_width(P.nrows ? (double)P.csr_nnz / P.nrows : 0);
+  const int var = P.prm.spmv_variant;
+  if (var <= 2) {
+    launch_stream(make_view(P, P.sched[var], false), 1 << var, x, y, s);
+    return;
+  }
+  const PlanView v = make_view(P, P.sched[0], false);
   const unsigned nb = (unsigned)v.ntiles;
-  switch (W) {
-    case 1: k_spmv_fused<1><<<nb, 256, 0, s>>>(v, x, y); break;
-    case 2: k_spmv_fused<2><<<nb, 256, 0, s>>>(v, x, y); break;
-    case 4: k_spmv_fused<4><<<nb, 256, 0, s>>>(v, x, y); break;
-    case 8: k_spmv_fused<8><<<nb, 256, 0, s>>>(v, x, y); break;
+  switch (var) {
+    case 3: k_spmv_fused<1><<<nb, 256, 0, s>>>(v, x, y); break;
+    case 4: k_spmv_fused<2><<<nb, 256, 0, s>>>(v, x, y); break;
+    case 5: k_spmv_fused<4><<<nb, 256, 0, s>>>(v, x, y); break;
+    case 6: k_spmv_fused<8><<<nb, 256, 0, s>>>(v, x, y); break;
     default: k_spmv_fused<16><<<nb, 256, 0, s>>>(v, x, y); break;
   }
   LAUNCH_CHECK();
 }
 
 void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
-  const int W = P.prm.plain_csr_width > 0 ? P.prm.plain_csr_width
-                                          : csr_width(P.nrows ? (double)P.nnz / P.nrows : 0);
+  const int var = P.prm.plain_variant;
+  if (var <= 2) {
+    launch_stream(make_view(P, P.sched_plain[var], true), 1 << var, x, y, s);
+    return;
+  }
+  const int W = 1 << (var - 3);
   const int rpb = 256 / W;
   const unsigned nb = (unsigned)((P.nrows + rpb - 1) / rpb);
   switch (W) {
@@ -273,9 +302,17 @@ void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStrea
 }
 
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s) {
-  const PlanView v = make_view(P, P.sched, false);
-  const unsigned nb = (unsigned)((P.nrows + 3) / 4);
-  k_spmm_fused_valu<<<nb, 256, 0, s>>>(v, X, Y, n);
+  const PlanView v = make_view(P, P.sched[0], false);
+  const int mode = P.prm.spmm_mode;
+  if (mode == 2) {
+    const unsigned nb = (unsigned)((P.nrows + 3) / 4);
+    k_spmm_fused_valu<<<nb, 256, 0, s>>>(v, X, Y, n);
+  } else {
+    const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
+    dim3 grid((unsigned)(((ntile + 7) / 8) * 8), (unsigned)((n + kMmCols - 1) / kMmCols));
+    const int mfma = (mode == 0 && P.vbr_hi.p != nullptr && P.nblk > 0) ? 1 : 0;
+    k_spmm_tile<<<grid, kMmThreads, 0, s>>>(v, X, Y, n, mfma);
+  }
   LAUNCH_CHECK();
 }
 

@@ -2,7 +2,6 @@
 #include "plan.h"
 
 extern "C" {
-sable_status sable_autotune(sable_plan_t, int32_t, int32_t, const float*, float*, void*) { return SABLE_ERR_INTERNAL; }
 sable_status sable_features(const sable_csr*, void*, float*) { return SABLE_ERR_INTERNAL; }
 sable_status sable_class_plan(int32_t, sable_extractor*, int32_t*, sable_thresholds*) { return SABLE_ERR_INTERNAL; }
 sable_status sable_mlp_forward(const float*, const float*, int32_t, float*, void*) { return SABLE_ERR_INTERNAL; }

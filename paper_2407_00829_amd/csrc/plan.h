@@ -24,11 +24,14 @@ struct BlkRec {  // block rectangle rows [r0, r1), columns [c0, c1)
 };
 
 // Launch parameters of the fused kernels (autotuned).
+// SpMV kernel variants: 0..2 = streamed tile body with 1, 2, 4 rows per thread (tiles of
+// 256, 512, 1024 rows); 3..7 = row-per-lane bands/blocks with 1, 2, 4, 8, 16 lanes per CSR
+// row (tiles of 256 rows). The plain CSR baseline uses the same numbering, 3..9 meaning
+// 1..64 lanes per row.
 struct ExecParams {
-  int spmv_rows_per_tile = 256;  // rows per workgroup tile of the fused SpMV
-  int spmv_csr_width = 0;        // lanes per CSR row in the fused SpMV (0: from row length)
-  int plain_csr_width = 0;       // lanes per row of the plain CSR baseline (0: from row length)
-  int spmm_mode = 0;             // fused SpMM variant
+  int spmv_variant = 1;
+  int plain_variant = 1;
+  int spmm_mode = 0;  // fused SpMM variant
 };
 
 struct Schedule {
@@ -67,8 +70,8 @@ struct sable_plan_s {
   sable::DBuf<int8_t> owner;
   sable::DBuf<sable::i64> slot;
   // schedule and tuned parameters
-  sable::Schedule sched;
-  sable::Schedule sched_plain;
+  sable::Schedule sched[3];        // tiles of 256, 512, 1024 rows with the formats
+  sable::Schedule sched_plain[3];  // the same tilings for the whole input as CSR
   sable::ExecParams prm;
   uint32_t flags = 0;
   double plan_ms = 0.0;

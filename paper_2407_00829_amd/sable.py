@@ -28,7 +28,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "INVALID_CSR", 3: "INCOMPLETE", 4: "TOO_
 EXPORTED = [
     "sable_thresholds_default", "sable_plan", "sable_plan_destroy", "sable_plan_info",
     "sable_plan_export", "sable_spmv", "sable_spmm", "sable_csr_spmv", "sable_error_norm_f64",
-    "sable_update_values", "sable_autotune", "sable_features", "sable_class_plan",
+    "sable_update_values", "sable_autotune", "sable_plan_set_variant", "sable_features", "sable_class_plan",
     "sable_mlp_forward", "sable_mlp_train_step", "sable_batch_create", "sable_batch_run",
     "sable_batch_latencies", "sable_batch_destroy", "sable_last_error",
 ]
@@ -105,6 +105,7 @@ def lib():
         "sable_error_norm_f64": [P, P, i64, P, P],
         "sable_update_values": [P, P, P],
         "sable_autotune": [P, i32, i32, P, P, P],
+        "sable_plan_set_variant": [P, i32, i32],
         "sable_features": [P, P, P],
         "sable_class_plan": [i32, P, P, P],
         "sable_mlp_forward": [P, P, i32, P, P],
@@ -268,6 +269,10 @@ def sable_error_norm_f64(y, yref, stream=None) -> float:
 def sable_autotune(p: Plan, op: int, n: int, x, y, stream=None) -> None:
     _check("sable_autotune", lib().sable_autotune(p.h, int(op), int(n), _ptr(x), _ptr(y),
                                                   _stream(stream)))
+
+
+def sable_plan_set_variant(p: Plan, op: int, variant: int) -> None:
+    _check("sable_plan_set_variant", lib().sable_plan_set_variant(p.h, int(op), int(variant)))
 
 
 def sable_features(nrows, ncols, indptr, indices, values, stream=None) -> np.ndarray:
