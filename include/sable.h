@@ -233,11 +233,31 @@ sable_status sable_mlp_forward(const float* params, const float* feats, int32_t 
 /* One training step of softmax cross-entropy with Adam (lr, beta1, beta2, eps; step t >= 1)
  * on a batch: feats[B][140], labels[B] (int32 class ids) -> params updated in place; grads
  * (SABLE_MLP_NPARAM) receives the batch-mean gradient; m, v Adam moments; *loss (host) the
- * batch-mean loss. Synchronises `stream`. */
+ * batch-mean loss. t = 0 computes the loss and the gradient only (no update; m, v unused).
+ * Synchronises `stream`. */
 sable_status sable_mlp_train_step(float* params, float* grads, float* m, float* v,
                                   const float* feats, const int32_t* labels, int32_t batch,
                                   float lr, float beta1, float beta2, float eps, int32_t t,
                                   void* stream, float* loss);
+
+/* Exhaustive timed search over the 15 classes (the fallback and judge of the learned
+ * planner): plans A with every class, times `reps` hybrid SpMV launches of each (median,
+ * after one warm-up) on `stream` and returns the fastest plan. x[ncols], y[nrows] are scratch
+ * device vectors; times_ms (host, SABLE_NCLASS entries, may be NULL) receives every class's
+ * time. Classes 0..2 (CSR only) share one plan; ties go to the lower class index. */
+sable_status sable_plan_exhaustive(const sable_csr* A, const float* x, float* y, int32_t reps,
+                                   void* stream, sable_plan_t* out, int32_t* best_class,
+                                   float* times_ms);
+
+/* Learned plan choice: features of A, normalised as (f - feat_mean) / feat_std (host arrays
+ * of SABLE_NFEAT), MLP forward with params (device, SABLE_MLP_NPARAM), softmax. If the top
+ * probability is >= tau_conf the top class is planned; otherwise the exhaustive search runs
+ * (x, y scratch as above). Outputs: the plan, the class used, the top probability and
+ * whether the fallback ran. */
+sable_status sable_plan_auto(const sable_csr* A, const float* params, const float* feat_mean,
+                             const float* feat_std, float tau_conf, const float* x, float* y,
+                             void* stream, sable_plan_t* out, int32_t* chosen_class,
+                             float* confidence, int32_t* fell_back);
 
 /* ---- Batched persistent execution ---------------------------------------------------- */
 typedef struct {

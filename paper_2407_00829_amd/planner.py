@@ -1,0 +1,266 @@
+"""Learned planner harness: labels from the exhaustive timed search, GPU training, regret.
+
+The planner replaces the search over extractor lists and delta thresholds with an MLP
+140-128-128-15 over structure features (diagonal run-length histogram, 16x16 tile density
+histogram, row-length statistics). All numerical work runs in libsable:
+  sable_features          features on the GPU
+  sable_plan_exhaustive   plans every class, times the fused SpMV, returns the fastest
+  sable_mlp_train_step    forward, softmax cross-entropy, backward and Adam on the GPU
+  sable_plan_auto         features -> MLP -> plan, exhaustive fallback below tau_conf
+This module only generates matrices, stores labels (append-only JSONL, resumable), loops
+over training batches and computes the summary statistics.
+
+Usage (GPU):
+  python -m paper_2407_00829_amd.planner label --out labels.jsonl --seeds 0:800
+  python -m paper_2407_00829_amd.planner train --labels labels.jsonl --train 0:600 --out w.npz
+  python -m paper_2407_00829_amd.planner eval --labels labels.jsonl --test 600:800 --weights w.npz
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import synth
+
+CLASS_LISTS = ["CSR", "VDIA+CSR", "VBR+CSR", "VDIA+VBR+CSR", "VBR+VDIA+CSR"]
+DELTAS = [500, 700, 900]
+NCLASS = 15
+
+
+def class_name(c: int) -> str:
+    return f"{CLASS_LISTS[c // 3]}@{DELTAS[c % 3] / 1000:.1f}"
+
+
+def matrix_params(seed: int, nmin: float = 1e4, nmax: float = 1.5e5):
+    """Planner matrix: n ~ logU[nmin, nmax], mean row length ~ U[4, 32], proportions ~
+    Dirichlet(1,1,1) over band / block / scatter generators."""
+    rng = np.random.default_rng(10_000_019 + seed)
+    n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+    rowlen = float(rng.uniform(4, 32))
+    pi = rng.dirichlet([1.0, 1.0, 1.0])
+    return n, rowlen, pi
+
+
+def make_matrix(seed: int):
+    n, rowlen, pi = matrix_params(seed)
+    A, x = synth.gen_mixed(seed, n=n, rowlen=rowlen, pi=pi)
+    return seed, A, x
+
+
+def _time_ms(fn, torch, reps=10):
+    fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def label_matrix(A, x, reps=10) -> dict:
+    import torch
+
+    from . import sable
+    ip, ix, vv = sable.device_csr(A)
+    f = sable.sable_features(A.nrows, A.ncols, ip, ix, vv)
+    xd = torch.from_numpy(x).cuda()
+    y = torch.empty(A.nrows, device="cuda")
+    p, best, times = sable.sable_plan_exhaustive(A.nrows, A.ncols, ip, ix, vv, xd, y, reps)
+    t_plain = _time_ms(lambda: sable.sable_csr_spmv(p, xd, y), torch, reps)
+    p.destroy()
+    th = sable.Thresholds(delta_band_pm=750, delta_block_pm=500)
+    q = sable.sable_plan(A.nrows, A.ncols, ip, ix, vv,
+                         [sable.SABLE_X_VDIA, sable.SABLE_X_VBR, sable.SABLE_X_CSR],
+                         sable.SABLE_VBR_TILED, th)
+    t_default = _time_ms(lambda: sable.sable_spmv(q, xd, y), torch, reps)
+    q.destroy()
+    return {"features": [float(v) for v in f], "times": [float(t) for t in times],
+            "best": int(best), "t_plain": t_plain, "t_default": t_default}
+
+
+def build_labels(seeds, path: str, workers: int = 8, reps: int = 10, log=print) -> int:
+    done = set()
+    if os.path.exists(path):
+        with open(path) as fh:
+            for line in fh:
+                try:
+                    done.add(json.loads(line)["seed"])
+                except (ValueError, KeyError):
+                    continue  # a torn last line from an interrupted run is ignored
+    todo = [s for s in seeds if s not in done]
+    log(f"[labels] {len(done)} cached, {len(todo)} to do")
+    n_new = 0
+    t0 = time.time()
+    with cf.ProcessPoolExecutor(workers) as ex, open(path, "a") as out:
+        for seed, A, x in ex.map(make_matrix, todo):
+            rec = label_matrix(A, x, reps)
+            rec.update(seed=int(seed), n=A.nrows, nnz=A.nnz)
+            out.write(json.dumps(rec) + "\n")
+            out.flush()
+            n_new += 1
+            if n_new % 25 == 0:
+                log(f"[labels] {n_new}/{len(todo)} ({time.time() - t0:.0f} s)")
+    return n_new
+
+
+def load_labels(path: str, seeds=None):
+    recs = []
+    with open(path) as fh:
+        for line in fh:
+            try:
+                r = json.loads(line)
+            except ValueError:
+                continue
+            if seeds is None or r["seed"] in seeds:
+                recs.append(r)
+    recs.sort(key=lambda r: r["seed"])
+    return recs
+
+
+def train(X: np.ndarray, y: np.ndarray, epochs: int = 300, batch: int = 64, lr: float = 1e-3,
+          seed: int = 0, init=None, log=print):
+    """Adam on the GPU (sable_mlp_train_step). Returns params, feature mean, feature std."""
+    import torch
+
+    from . import sable
+    mean = X.mean(axis=0).astype(np.float32)
+    std = X.std(axis=0).astype(np.float32)
+    std[std < 1e-6] = 1.0
+    Xn = ((X - mean) / std).astype(np.float32)
+    if init is None:
+        rng = np.random.default_rng(seed)
+        parts = []
+        for rows, cols in ((128, 140), (128, 128), (15, 128)):
+            lim = math.sqrt(6.0 / cols)
+            parts.append(rng.uniform(-lim, lim, rows * cols))
+            parts.append(np.zeros(rows))
+        init = np.concatenate(parts).astype(np.float32)
+    P = torch.from_numpy(init.copy()).cuda()
+    G = torch.zeros_like(P)
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    Xd = torch.from_numpy(Xn).cuda()
+    yd = torch.from_numpy(y.astype(np.int32)).cuda()
+    rng = np.random.default_rng(seed + 1)
+    t = 0
+    hist = []
+    for ep in range(epochs):
+        perm = rng.permutation(Xn.shape[0])
+        tot = 0.0
+        for b0 in range(0, perm.size, batch):
+            idx = torch.from_numpy(perm[b0:b0 + batch]).cuda()
+            t += 1
+            loss = sable.sable_mlp_train_step(P, G, M, V, Xd[idx].contiguous(),
+                                              yd[idx].contiguous(), lr, 0.9, 0.999, 1e-8, t)
+            tot += loss * idx.numel()
+        hist.append(tot / perm.size)
+        if log and (ep % 50 == 0 or ep == epochs - 1):
+            log(f"[train] epoch {ep} loss {hist[-1]:.4f}")
+    return P.cpu().numpy(), mean, std, hist
+
+
+def predict(params, mean, std, X):
+    import torch
+
+    from . import sable
+    Xn = ((X - mean) / std).astype(np.float32)
+    Pd = torch.from_numpy(params).cuda()
+    Xd = torch.from_numpy(Xn).cuda()
+    L = torch.empty(X.shape[0], NCLASS, device="cuda")
+    sable.sable_mlp_forward(Pd, Xd, L)
+    torch.cuda.synchronize()
+    z = L.cpu().numpy().astype(np.float64)
+    z -= z.max(axis=1, keepdims=True)
+    pr = np.exp(z)
+    pr /= pr.sum(axis=1, keepdims=True)
+    return pr.argmax(axis=1), pr.max(axis=1)
+
+
+def evaluate(params, mean, std, recs, tau_conf: float = 0.0) -> dict:
+    """Regret t(pred)/t(best) - 1 over held-out records; below tau_conf the exhaustive search
+    decides (regret 0 for that matrix, counted as a fallback). Gains are geomean speedups of
+    the chosen plan over the fixed default plan and over plain CSR."""
+    X = np.array([r["features"] for r in recs], np.float32)
+    pred, conf = predict(params, mean, std, X)
+    regret, g_def, g_plain, fb = [], [], [], 0
+    for r, c, cf_ in zip(recs, pred, conf):
+        t = np.array(r["times"])
+        if cf_ < tau_conf:
+            c = int(np.argmin(t))
+            fb += 1
+        regret.append(t[c] / t.min() - 1.0)
+        g_def.append(r["t_default"] / t[c])
+        g_plain.append(r["t_plain"] / t[c])
+    regret = np.array(regret)
+    oracle_best = np.array([np.min(r["times"]) for r in recs])
+    return {"n": len(recs), "regret_mean": float(regret.mean()),
+            "regret_p90": float(np.percentile(regret, 90)),
+            "accuracy": float(np.mean([np.argmin(r["times"]) == c for r, c in zip(recs, pred)])),
+            "gain_vs_default_geomean": float(np.exp(np.mean(np.log(g_def)))),
+            "gain_vs_plain_csr_geomean": float(np.exp(np.mean(np.log(g_plain)))),
+            "best_vs_plain_geomean": float(np.exp(np.mean(np.log(
+                [r["t_plain"] / b for r, b in zip(recs, oracle_best)])))),
+            "fallback_rate": fb / max(1, len(recs)), "tau_conf": tau_conf}
+
+
+def save_weights(path, params, mean, std):
+    np.savez(path, params=params.astype(np.float32), mean=mean.astype(np.float32),
+             std=std.astype(np.float32))
+
+
+def load_weights(path):
+    z = np.load(path)
+    return z["params"], z["mean"], z["std"]
+
+
+def _range(s: str):
+    a, b = s.split(":")
+    return list(range(int(a), int(b)))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("label")
+    a.add_argument("--out", required=True)
+    a.add_argument("--seeds", required=True)
+    a.add_argument("--workers", type=int, default=8)
+    a.add_argument("--reps", type=int, default=10)
+    b = sub.add_parser("train")
+    b.add_argument("--labels", required=True)
+    b.add_argument("--train", required=True)
+    b.add_argument("--out", required=True)
+    b.add_argument("--epochs", type=int, default=300)
+    c = sub.add_parser("eval")
+    c.add_argument("--labels", required=True)
+    c.add_argument("--test", required=True)
+    c.add_argument("--weights", required=True)
+    c.add_argument("--tau", type=float, default=0.0)
+    args = ap.parse_args(argv)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    if args.cmd == "label":
+        build_labels(_range(args.seeds), args.out, args.workers, args.reps, log)
+    elif args.cmd == "train":
+        recs = load_labels(args.labels, set(_range(args.train)))
+        X = np.array([r["features"] for r in recs], np.float32)
+        y = np.array([r["best"] for r in recs], np.int32)
+        params, mean, std, hist = train(X, y, epochs=args.epochs, log=log)
+        save_weights(args.out, params, mean, std)
+        print(json.dumps({"trained_on": len(recs), "final_loss": hist[-1]}))
+    else:
+        recs = load_labels(args.labels, set(_range(args.test)))
+        params, mean, std = load_weights(args.weights)
+        print(json.dumps(evaluate(params, mean, std, recs, args.tau)))
+
+
+if __name__ == "__main__":
+    main()

@@ -29,7 +29,7 @@ EXPORTED = [
     "sable_thresholds_default", "sable_plan", "sable_plan_destroy", "sable_plan_info",
     "sable_plan_export", "sable_spmv", "sable_spmm", "sable_csr_spmv", "sable_error_norm_f64",
     "sable_update_values", "sable_autotune", "sable_plan_set_variant", "sable_features", "sable_class_plan",
-    "sable_mlp_forward", "sable_mlp_train_step", "sable_batch_create", "sable_batch_run",
+    "sable_mlp_forward", "sable_mlp_train_step", "sable_plan_exhaustive", "sable_plan_auto", "sable_batch_create", "sable_batch_run",
     "sable_batch_latencies", "sable_batch_destroy", "sable_last_error",
 ]
 
@@ -111,6 +111,8 @@ def lib():
         "sable_mlp_forward": [P, P, i32, P, P],
         "sable_mlp_train_step": [P, P, P, P, P, P, i32, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, i32, P, P],
+        "sable_plan_exhaustive": [P, P, P, i32, P, P, P, P],
+        "sable_plan_auto": [P, P, P, P, ctypes.c_float, P, P, P, P, P, P, P],
         "sable_batch_create": [P, P, i32, P, P],
         "sable_batch_run": [P, P],
         "sable_batch_latencies": [P, P, P],
@@ -309,6 +311,35 @@ def sable_mlp_train_step(params, grads, m, v, feats, labels, lr, beta1, beta2, e
         int(feats.shape[0]), float(lr), float(beta1), float(beta2), float(eps), int(t),
         _stream(stream), ctypes.byref(loss)))
     return loss.value
+
+
+def sable_plan_exhaustive(nrows, ncols, indptr, indices, values, x, y, reps=10, stream=None):
+    """Returns (Plan, best_class, times_ms[15])."""
+    A = csr_struct(nrows, ncols, indptr, indices, values)
+    h = ctypes.c_void_p()
+    bc = ctypes.c_int32()
+    times = np.zeros(SABLE_NCLASS, np.float32)
+    _check("sable_plan_exhaustive", lib().sable_plan_exhaustive(
+        ctypes.byref(A), _ptr(x), _ptr(y), int(reps), _stream(stream), ctypes.byref(h),
+        ctypes.byref(bc), times.ctypes.data_as(ctypes.c_void_p)))
+    return Plan(h, int(nrows), int(ncols), int(indices.numel())), bc.value, times
+
+
+def sable_plan_auto(nrows, ncols, indptr, indices, values, params, feat_mean, feat_std,
+                    tau_conf, x, y, stream=None):
+    """Returns (Plan, chosen_class, confidence, fell_back)."""
+    A = csr_struct(nrows, ncols, indptr, indices, values)
+    fm = np.ascontiguousarray(feat_mean, np.float32)
+    fs = np.ascontiguousarray(feat_std, np.float32)
+    h = ctypes.c_void_p()
+    c = ctypes.c_int32()
+    conf = ctypes.c_float()
+    fb = ctypes.c_int32()
+    _check("sable_plan_auto", lib().sable_plan_auto(
+        ctypes.byref(A), _ptr(params), fm.ctypes.data_as(ctypes.c_void_p),
+        fs.ctypes.data_as(ctypes.c_void_p), float(tau_conf), _ptr(x), _ptr(y), _stream(stream),
+        ctypes.byref(h), ctypes.byref(c), ctypes.byref(conf), ctypes.byref(fb)))
+    return Plan(h, int(nrows), int(ncols), int(indices.numel())), c.value, conf.value, bool(fb.value)
 
 
 class Batch:

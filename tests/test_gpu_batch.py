@@ -1,0 +1,73 @@
+"""Batched persistent hipGraph launch: every item bitwise equal to its standalone launch,
+across several graph replays with eager work in between; latencies are recorded."""
+import numpy as np
+import pytest
+
+from paper_2407_00829_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2407_00829_amd import sable  # noqa: E402
+
+
+def make_items(count, seed=0):
+    rng = np.random.default_rng(seed)
+    plans, items, refs = [], [], []
+    kinds = [sable.SABLE_X_VDIA, sable.SABLE_X_VBR, sable.SABLE_X_CSR]
+    for i in range(count):
+        n = int(np.exp(rng.uniform(np.log(500), np.log(30000))))
+        A, x = synth.gen_mixed(1000 + i, n=n, rowlen=float(rng.uniform(4, 20)),
+                               pi=rng.dirichlet([1, 1, 1]))
+        p = sable.plan_host(A, kinds, sable.SABLE_VBR_TILED,
+                            sable.Thresholds(amin_band=256, amin_block=64))
+        op = int(rng.integers(0, 2))
+        if op == 0:
+            sable.sable_plan_set_variant(p, 0, int(rng.integers(0, 3)))
+            xd = torch.from_numpy(x).cuda()
+            yd = torch.full((n,), float("nan"), device="cuda")
+            items.append((0, 1, xd, yd))
+        else:
+            X = torch.from_numpy(synth.gen_dense_matrix(i, n, 16)).cuda()
+            Y = torch.full((n, 16), float("nan"), device="cuda")
+            items.append((1, 16, X, Y))
+        plans.append(p)
+    return plans, items
+
+
+def standalone(plans, items):
+    outs = []
+    for p, (op, n, x, y) in zip(plans, items):
+        z = torch.empty_like(y)
+        if op == 0:
+            sable.sable_spmv(p, x, z)
+        else:
+            sable.sable_spmm(p, x, z, n)
+        outs.append(z)
+    torch.cuda.synchronize()
+    return outs
+
+
+def test_batch_bitwise_equal_and_replays():
+    plans, items = make_items(24)
+    ref = standalone(plans, items)
+    b = sable.sable_batch_create(plans, items)
+    for rep in range(3):
+        for (_, _, _, y) in items:
+            y.fill_(float("nan"))  # eager work between replays
+        sable.sable_batch_run(b)
+        torch.cuda.synchronize()
+        for i, ((_, _, _, y), r) in enumerate(zip(items, ref)):
+            assert torch.equal(y, r), (rep, i)
+        ticks, hz = sable.sable_batch_latencies(b)
+        assert hz > 0 and np.all(ticks > 0)
+    b.destroy()
+
+
+def test_batch_rejects_bad_items():
+    plans, items = make_items(2, seed=5)
+    bad = [(0, 2, items[0][2], items[0][3])] + items[1:]
+    with pytest.raises(sable.SableError):
+        sable.sable_batch_create(plans, bad)
