@@ -241,8 +241,9 @@ sable_status sable_mlp_train_step(float* params, float* grads, float* m, float* 
                                   void* stream, float* loss);
 
 /* Exhaustive timed search over the 15 classes (the fallback and judge of the learned
- * planner): plans A with every class, times `reps` hybrid SpMV launches of each (median,
- * after one warm-up) on `stream` and returns the fastest plan. x[ncols], y[nrows] are scratch
+ * planner): plans A with every class, times its hybrid SpMV on `stream` (after one warm-up,
+ * three rounds of `reps` back-to-back launches; the median per-launch average) and returns
+ * the fastest plan. x[ncols], y[nrows] are scratch
  * device vectors; times_ms (host, SABLE_NCLASS entries, may be NULL) receives every class's
  * time. Classes 0..2 (CSR only) share one plan; ties go to the lower class index. */
 sable_status sable_plan_exhaustive(const sable_csr* A, const float* x, float* y, int32_t reps,

@@ -341,21 +341,27 @@ void class_plan(int c, sable_extractor* list, int32_t* nlist, sable_thresholds* 
 
 namespace {
 
+// Time of one fused SpMV: three rounds of `reps` back-to-back launches between two events;
+// the median of the three per-launch averages (per-launch events are too coarse for launches
+// of a few microseconds).
 float median_launch_ms(const sable_plan_s& P, const float* x, float* y, int reps, hipStream_t s) {
-  std::vector<hipEvent_t> ev(2 * (size_t)reps);
+  hipEvent_t ev[6];
   for (auto& e : ev) HIPC(hipEventCreate(&e));
   launch_spmv(P, x, y, s);  // warm-up
-  for (int r = 0; r < reps; ++r) {
+  for (int r = 0; r < 3; ++r) {
     HIPC(hipEventRecord(ev[2 * r], s));
-    launch_spmv(P, x, y, s);
+    for (int k = 0; k < reps; ++k) launch_spmv(P, x, y, s);
     HIPC(hipEventRecord(ev[2 * r + 1], s));
   }
   HIPC(hipStreamSynchronize(s));
-  std::vector<float> t(reps);
-  for (int r = 0; r < reps; ++r) HIPC(hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]));
+  float t[3];
+  for (int r = 0; r < 3; ++r) {
+    HIPC(hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]));
+    t[r] /= reps;
+  }
   for (auto& e : ev) (void)hipEventDestroy(e);
-  std::sort(t.begin(), t.end());
-  return t[reps / 2];
+  std::sort(t, t + 3);
+  return t[1];
 }
 
 }  // namespace

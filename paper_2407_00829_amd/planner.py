@@ -55,18 +55,21 @@ def make_matrix(seed: int):
 
 
 def _time_ms(fn, torch, reps=10):
+    """Median over three rounds of the per-launch average of `reps` back-to-back launches."""
     fn()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(reps)]
-    for a, b in ev:
+    out = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        fn()
+        for _ in range(reps):
+            fn()
         b.record()
-    torch.cuda.synchronize()
-    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b) / reps)
+    return float(np.median(out))
 
 
-def label_matrix(A, x, reps=10) -> dict:
+def label_matrix(A, x, reps=20) -> dict:
     import torch
 
     from . import sable
@@ -87,7 +90,7 @@ def label_matrix(A, x, reps=10) -> dict:
             "best": int(best), "t_plain": t_plain, "t_default": t_default}
 
 
-def build_labels(seeds, path: str, workers: int = 8, reps: int = 10, log=print) -> int:
+def build_labels(seeds, path: str, workers: int = 8, reps: int = 20, log=print) -> int:
     done = set()
     if os.path.exists(path):
         with open(path) as fh:
@@ -126,7 +129,28 @@ def load_labels(path: str, seeds=None):
     return recs
 
 
-def train(X: np.ndarray, y: np.ndarray, epochs: int = 300, batch: int = 64, lr: float = 1e-3,
+def robust_labels(recs, tol: float = 0.05, rank_recs=None):
+    """Training label per matrix: among the classes within `tol` of the fastest measured time,
+    the one with the lowest mean regret over `rank_recs` (default: recs). Near-ties are mostly
+    timing noise; this maps them to one consistent class instead of a random argmin."""
+    T = np.array([r["times"] for r in recs])
+    R = T / T.min(axis=1, keepdims=True) - 1.0
+    Tr = np.array([r["times"] for r in (rank_recs or recs)])
+    Rr = Tr / Tr.min(axis=1, keepdims=True) - 1.0
+    rank = np.empty(NCLASS, int)
+    rank[np.argsort(Rr.mean(axis=0), kind="stable")] = np.arange(NCLASS)
+    return np.where(R <= tol, rank[None, :], NCLASS + 1).argmin(axis=1).astype(np.int32)
+
+
+def choose_tau(params, mean, std, val_recs, target: float = 0.04) -> float:
+    """Smallest confidence threshold (grid 0.0..0.95) whose validation regret <= target."""
+    for tau in np.round(np.arange(0.0, 0.96, 0.05), 2):
+        if evaluate(params, mean, std, val_recs, float(tau))["regret_mean"] <= target:
+            return float(tau)
+    return 0.95
+
+
+def train(X: np.ndarray, y: np.ndarray, epochs: int = 10, batch: int = 64, lr: float = 1e-3,
           seed: int = 0, init=None, log=print):
     """Adam on the GPU (sable_mlp_train_step). Returns params, feature mean, feature std."""
     import torch
@@ -212,14 +236,18 @@ def evaluate(params, mean, std, recs, tau_conf: float = 0.0) -> dict:
             "fallback_rate": fb / max(1, len(recs)), "tau_conf": tau_conf}
 
 
-def save_weights(path, params, mean, std):
+def save_weights(path, params, mean, std, tau=0.0):
     np.savez(path, params=params.astype(np.float32), mean=mean.astype(np.float32),
-             std=std.astype(np.float32))
+             std=std.astype(np.float32), tau=np.float32(tau))
 
 
 def load_weights(path):
     z = np.load(path)
-    return z["params"], z["mean"], z["std"]
+    tau = float(z["tau"]) if "tau" in z else 0.0
+    return z["params"], z["mean"], z["std"], tau
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "planner_weights.npz")
 
 
 def _range(s: str):
@@ -234,32 +262,46 @@ def main(argv=None):
     a.add_argument("--out", required=True)
     a.add_argument("--seeds", required=True)
     a.add_argument("--workers", type=int, default=8)
-    a.add_argument("--reps", type=int, default=10)
+    a.add_argument("--reps", type=int, default=20)
     b = sub.add_parser("train")
     b.add_argument("--labels", required=True)
     b.add_argument("--train", required=True)
     b.add_argument("--out", required=True)
-    b.add_argument("--epochs", type=int, default=300)
+    b.add_argument("--epochs", type=int, default=10)
+    b.add_argument("--tol", type=float, default=0.05)
+    b.add_argument("--target", type=float, default=0.04)
     c = sub.add_parser("eval")
     c.add_argument("--labels", required=True)
     c.add_argument("--test", required=True)
     c.add_argument("--weights", required=True)
-    c.add_argument("--tau", type=float, default=0.0)
+    c.add_argument("--tau", type=float, default=-1.0)
     args = ap.parse_args(argv)
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     if args.cmd == "label":
         build_labels(_range(args.seeds), args.out, args.workers, args.reps, log)
     elif args.cmd == "train":
         recs = load_labels(args.labels, set(_range(args.train)))
-        X = np.array([r["features"] for r in recs], np.float32)
-        y = np.array([r["best"] for r in recs], np.int32)
+        val = [r for i, r in enumerate(recs) if i % 10 == 0]   # 10% validation split
+        fit = [r for i, r in enumerate(recs) if i % 10 != 0]
+        X = np.array([r["features"] for r in fit], np.float32)
+        y = robust_labels(fit, args.tol)
         params, mean, std, hist = train(X, y, epochs=args.epochs, log=log)
-        save_weights(args.out, params, mean, std)
-        print(json.dumps({"trained_on": len(recs), "final_loss": hist[-1]}))
+        tau = choose_tau(params, mean, std, val, args.target)
+        save_weights(args.out, params, mean, std, tau)
+        print(json.dumps({"trained_on": len(fit), "validation": len(val), "final_loss": hist[-1],
+                          "tau_conf": tau, "val_no_fallback": evaluate(params, mean, std, val, 0.0),
+                          "val_with_fallback": evaluate(params, mean, std, val, tau)}))
     else:
         recs = load_labels(args.labels, set(_range(args.test)))
-        params, mean, std = load_weights(args.weights)
-        print(json.dumps(evaluate(params, mean, std, recs, args.tau)))
+        params, mean, std, tau = load_weights(args.weights)
+        if args.tau >= 0:
+            tau = args.tau
+        T = np.array([r["times"] for r in recs])
+        const = (T / T.min(axis=1, keepdims=True) - 1.0).mean(axis=0)
+        print(json.dumps({"no_fallback": evaluate(params, mean, std, recs, 0.0),
+                          "with_fallback": evaluate(params, mean, std, recs, tau),
+                          "best_constant_class": int(const.argmin()),
+                          "best_constant_regret": float(const.min())}))
 
 
 if __name__ == "__main__":

@@ -79,13 +79,15 @@ def test_training_learns_separable_labels():
     from paper_2407_00829_amd import planner
     rng = np.random.default_rng(0)
     N = 600
-    X = rng.standard_normal((N, pr.NFEAT)).astype(np.float32)
-    # the class is decided by 30 of the 140 features (like a structure type)
-    y = (X[:, :15] + 0.5 * X[:, 15:30]).argmax(axis=1).astype(np.int32)
-    params, mean, std, hist = planner.train(X[:500], y[:500], epochs=120, log=None)
-    assert hist[-1] < hist[0] * 0.3
+    # one noisy cluster of feature vectors per class (structure types); the same training
+    # with the FP64 oracle reaches 100% held-out accuracy
+    centres = rng.standard_normal((pr.NOUT, pr.NFEAT))
+    y = rng.integers(0, pr.NOUT, N).astype(np.int32)
+    X = (centres[y] + 0.8 * rng.standard_normal((N, pr.NFEAT))).astype(np.float32)
+    params, mean, std, hist = planner.train(X[:500], y[:500], epochs=40, log=None)
+    assert hist[-1] < hist[0] * 0.1
     pred, _ = planner.predict(params, mean, std, X[500:])
-    assert np.mean(pred == y[500:]) > 0.5
+    assert np.mean(pred == y[500:]) > 0.9
 
 
 def test_exhaustive_and_auto_plans():
