@@ -128,6 +128,7 @@ def run_spmv(args, torch, sable, synth, oracle):
     yp = torch.empty(A.nrows, device="cuda")
     if args.autotune:
         sable.sable_autotune(p, 0, 1, xd, y)
+    info = sable.sable_plan_info(p)
     f_h = lambda: sable.sable_spmv(p, xd, y)  # noqa: E731
     f_p = lambda: sable.sable_csr_spmv(p, xd, yp)  # noqa: E731
     wall, ev_ms = timed_steps(f_h, args.steps, args.warmup, torch)
@@ -169,6 +170,7 @@ def run_spmv(args, torch, sable, synth, oracle):
                  "speedup": round(cold_p / cold, 4)},
         "plan_ms": round(info["plan_ms"], 1), "plan_wall_s": round(plan_wall, 2),
         "partition": {k: info[k] for k in ("nseg", "vdia_nnz", "nblk", "vbr_nnz", "csr_nnz")},
+        "variants": {"hybrid": info["spmv_variant"], "plain": info["plain_variant"]},
     }
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")

@@ -118,6 +118,8 @@ typedef struct {
   int64_t bytes_matrix;    /* algorithmic matrix bytes of one product (formats only) */
   int64_t device_bytes;    /* device memory held by the plan */
   double plan_ms;          /* wall time of sable_plan */
+  int32_t spmv_variant, spmm_variant, plain_variant; /* kernel variants in use */
+  int32_t pad1;
 } sable_plan_stats;
 
 /* Host buffers for sable_plan_export, sized from sable_plan_info:
@@ -200,9 +202,10 @@ sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, const float* 
 
 /* Select a fused-kernel variant explicitly (the set sable_autotune chooses from).
  * op 0 = hybrid SpMV: 0..2 streamed tiles of 256/512/1024 rows, 3..7 row-per-lane with
- *        1/2/4/8/16 lanes per CSR row;
+ *        1/2/4/8/16 lanes per CSR row, 8..10 = 0..2 with non-temporal matrix loads;
  * op 1 = SpMM: 0 tiled with matrix-core blocks, 1 tiled fp32, 2 one wave per row;
- * op 2 = plain CSR baseline: 0..2 streamed, 3..9 with 1..64 lanes per row.
+ * op 2 = plain CSR baseline: 0..2 streamed, 3..9 with 1..64 lanes per row, 10..12 = 0..2
+ *        with non-temporal matrix loads.
  * Every variant computes the same product; each is bitwise reproducible on its own. */
 sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32_t variant);
 

@@ -266,6 +266,9 @@ sable_status sable_plan_info(sable_plan_t p, sable_plan_stats* o) {
                       8 * p->csr_nnz + 4 * ((i64)p->nrows + 1);
     o->device_bytes = p->device_bytes();
     o->plan_ms = p->plan_ms;
+    o->spmv_variant = p->prm.spmv_variant;
+    o->spmm_variant = p->prm.spmm_mode;
+    o->plain_variant = p->prm.plain_variant;
   });
 }
 

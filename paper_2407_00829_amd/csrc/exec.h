@@ -116,7 +116,15 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
   return (bid & 7) * per + (bid >> 3);
 }
 
-template <int RPT>
+// Matrix values and indices are read exactly once per product; with NT they are loaded with
+// the non-temporal hint so they do not evict x (the only reused operand) from the L2.
+template <bool NT, class T>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <int RPT, bool NT = false>
 __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
                                                  const float* __restrict__ x,
                                                  float* __restrict__ y, float* __restrict__ lds) {
@@ -143,8 +151,8 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
       int d = 0;
       for (; d + 4 <= nd; d += 4) {
         const int c0 = r + od[d], c1 = r + od[d + 1], c2 = r + od[d + 2], c3 = r + od[d + 3];
-        const float v0 = v[(i64)d * nr], v1 = v[(i64)(d + 1) * nr], v2 = v[(i64)(d + 2) * nr],
-                    v3 = v[(i64)(d + 3) * nr];
+        const float v0 = ld<NT>(v + (i64)d * nr), v1 = ld<NT>(v + (i64)(d + 1) * nr),
+                    v2 = ld<NT>(v + (i64)(d + 2) * nr), v3 = ld<NT>(v + (i64)(d + 3) * nr);
         const float x0 = (unsigned)c0 < (unsigned)P.ncols ? x[c0] : 0.f;
         const float x1 = (unsigned)c1 < (unsigned)P.ncols ? x[c1] : 0.f;
         const float x2 = (unsigned)c2 < (unsigned)P.ncols ? x[c2] : 0.f;
@@ -156,7 +164,7 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
       }
       for (; d < nd; ++d) {
         const int c = r + od[d];
-        if ((unsigned)c < (unsigned)P.ncols) acc[q] += v[(i64)d * nr] * x[c];
+        if ((unsigned)c < (unsigned)P.ncols) acc[q] += ld<NT>(v + (i64)d * nr) * x[c];
       }
     }
   }
@@ -179,15 +187,28 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
       const int row = lo + rl;
       const int cb = c0 + sl * cw, ce = min(c1, cb + cw);
       const float* v = vb + (row - br0);
-      float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+      float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f;
       int c = cb;
-      for (; c + 4 <= ce; c += 4) {
-        p0 += v[(i64)(c - c0) * h] * x[c];
-        p1 += v[(i64)(c + 1 - c0) * h] * x[c + 1];
-        p2 += v[(i64)(c + 2 - c0) * h] * x[c + 2];
-        p3 += v[(i64)(c + 3 - c0) * h] * x[c + 3];
+      for (; c + 8 <= ce; c += 8) {
+        const float* vc = v + (i64)(c - c0) * h;
+        const float a0 = ld<NT>(vc), a1 = ld<NT>(vc + h), a2 = ld<NT>(vc + 2 * (i64)h),
+                    a3 = ld<NT>(vc + 3 * (i64)h), a4 = ld<NT>(vc + 4 * (i64)h),
+                    a5 = ld<NT>(vc + 5 * (i64)h), a6 = ld<NT>(vc + 6 * (i64)h),
+                    a7 = ld<NT>(vc + 7 * (i64)h);
+        p0 += a0 * x[c];
+        p1 += a1 * x[c + 1];
+        p2 += a2 * x[c + 2];
+        p3 += a3 * x[c + 3];
+        p4 += a4 * x[c + 4];
+        p5 += a5 * x[c + 5];
+        p6 += a6 * x[c + 6];
+        p7 += a7 * x[c + 7];
       }
-      for (; c < ce; ++c) p0 += v[(i64)(c - c0) * h] * x[c];
+      for (; c < ce; ++c) p0 += ld<NT>(v + (i64)(c - c0) * h) * x[c];
+      p0 += p4;
+      p1 += p5;
+      p2 += p6;
+      p3 += p7;
       part[i] = (p0 + p1) + (p2 + p3);
     }
     __syncthreads();
@@ -217,14 +238,16 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
     int i = t;
     for (; i + 3 * kSpmvThreads < n; i += 4 * kSpmvThreads) {
       const int k0 = e0 + i, k1 = k0 + kSpmvThreads, k2 = k1 + kSpmvThreads, k3 = k2 + kSpmvThreads;
-      const int j0 = P.csr_col[k0], j1 = P.csr_col[k1], j2 = P.csr_col[k2], j3 = P.csr_col[k3];
-      const float a0 = P.csr_val[k0], a1 = P.csr_val[k1], a2 = P.csr_val[k2], a3 = P.csr_val[k3];
+      const int j0 = ld<NT>(P.csr_col + k0), j1 = ld<NT>(P.csr_col + k1),
+                j2 = ld<NT>(P.csr_col + k2), j3 = ld<NT>(P.csr_col + k3);
+      const float a0 = ld<NT>(P.csr_val + k0), a1 = ld<NT>(P.csr_val + k1),
+                  a2 = ld<NT>(P.csr_val + k2), a3 = ld<NT>(P.csr_val + k3);
       prod[i] = a0 * x[j0];
       prod[i + kSpmvThreads] = a1 * x[j1];
       prod[i + 2 * kSpmvThreads] = a2 * x[j2];
       prod[i + 3 * kSpmvThreads] = a3 * x[j3];
     }
-    for (; i < n; i += kSpmvThreads) prod[i] = P.csr_val[e0 + i] * x[P.csr_col[e0 + i]];
+    for (; i < n; i += kSpmvThreads) prod[i] = ld<NT>(P.csr_val + e0 + i) * x[ld<NT>(P.csr_col + e0 + i)];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {

@@ -121,13 +121,13 @@ __global__ __launch_bounds__(256) void k_spmv_fused(PlanView P, const float* __r
   spmv_tile<W>(P, blockIdx.x, x, y, part);
 }
 
-template <int RPT>
+template <int RPT, bool NT>
 __global__ __launch_bounds__(256) void k_spmv_stream(PlanView P, const float* __restrict__ x,
                                                     float* __restrict__ y) {
   __shared__ float lds[kCsrChunk + kSpmvThreads * RPT];
   const int tile = xcd_tile(blockIdx.x, P.ntiles);
   if (tile >= P.ntiles) return;
-  spmv_tile_stream<RPT>(P, tile, x, y, lds);
+  spmv_tile_stream<RPT, NT>(P, tile, x, y, lds);
 }
 
 template <int W>
@@ -252,20 +252,30 @@ void build_bf16_split(sable_plan_s& P, hipStream_t s) {
   }
 }
 
-static void launch_stream(const PlanView& v, int rpt, const float* x, float* y, hipStream_t s) {
+static void launch_stream(const PlanView& v, int rpt, bool nt, const float* x, float* y,
+                          hipStream_t s) {
   const unsigned nb = (unsigned)(((v.ntiles + 7) / 8) * 8);
-  switch (rpt) {
-    case 1: k_spmv_stream<1><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
-    case 2: k_spmv_stream<2><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
-    default: k_spmv_stream<4><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+  if (nt) {
+    switch (rpt) {
+      case 1: k_spmv_stream<1, true><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+      case 2: k_spmv_stream<2, true><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+      default: k_spmv_stream<4, true><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+    }
+  } else {
+    switch (rpt) {
+      case 1: k_spmv_stream<1, false><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+      case 2: k_spmv_stream<2, false><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+      default: k_spmv_stream<4, false><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+    }
   }
   LAUNCH_CHECK();
 }
 
 void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
   const int var = P.prm.spmv_variant;
-  if (var <= 2) {
-    launch_stream(make_view(P, P.sched[var], false), 1 << var, x, y, s);
+  if (var <= 2 || var >= 8) {
+    const int k = var <= 2 ? var : var - 8;
+    launch_stream(make_view(P, P.sched[k], false), 1 << k, var >= 8, x, y, s);
     return;
   }
   const PlanView v = make_view(P, P.sched[0], false);
@@ -282,8 +292,9 @@ void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s)
 
 void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
   const int var = P.prm.plain_variant;
-  if (var <= 2) {
-    launch_stream(make_view(P, P.sched_plain[var], true), 1 << var, x, y, s);
+  if (var <= 2 || var >= 10) {
+    const int k = var <= 2 ? var : var - 10;
+    launch_stream(make_view(P, P.sched_plain[k], true), 1 << k, var >= 10, x, y, s);
     return;
   }
   const int W = 1 << (var - 3);

@@ -26,8 +26,8 @@ struct BlkRec {  // block rectangle rows [r0, r1), columns [c0, c1)
 // Launch parameters of the fused kernels (autotuned).
 // SpMV kernel variants: 0..2 = streamed tile body with 1, 2, 4 rows per thread (tiles of
 // 256, 512, 1024 rows); 3..7 = row-per-lane bands/blocks with 1, 2, 4, 8, 16 lanes per CSR
-// row (tiles of 256 rows). The plain CSR baseline uses the same numbering, 3..9 meaning
-// 1..64 lanes per row.
+// row (tiles of 256 rows); 8..10 = 0..2 with non-temporal matrix loads. The plain CSR
+// baseline: 0..2 streamed, 3..9 = 1..64 lanes per row, 10..12 = 0..2 non-temporal.
 struct ExecParams {
   int spmv_variant = 1;
   int plain_variant = 1;

@@ -33,7 +33,7 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
   if (op == 0) {
     float best = 1e30f;
     int bv = 0;
-    for (int v = 0; v <= 7; ++v) {
+    for (int v = 0; v <= 10; ++v) {
       P.prm.spmv_variant = v;
       float t = time_ms([&] { launch_spmv(P, x, y, s); }, s, reps);
       if (t < best) { best = t; bv = v; }
@@ -41,7 +41,7 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
     P.prm.spmv_variant = bv;
     best = 1e30f;
     bv = 0;
-    for (int v = 0; v <= 9; ++v) {
+    for (int v = 0; v <= 12; ++v) {
       P.prm.plain_variant = v;
       float t = time_ms([&] { launch_spmv_plain(P, x, y, s); }, s, reps);
       if (t < best) { best = t; bv = v; }
@@ -87,7 +87,7 @@ extern "C" sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32
     sable::set_error("NULL plan");
     return SABLE_ERR_INVALID_ARG;
   }
-  const int maxv = op == 0 ? 7 : op == 1 ? 2 : op == 2 ? 9 : -1;
+  const int maxv = op == 0 ? 10 : op == 1 ? 2 : op == 2 ? 12 : -1;
   if (variant < 0 || variant > maxv) {
     sable::set_error("variant %d out of range for op %d", variant, op);
     return SABLE_ERR_INVALID_ARG;

@@ -207,12 +207,12 @@ def test_every_spmv_variant_and_baseline():
     p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
     ref = oracle.spmv(A, x)
     xd = torch.from_numpy(x).cuda()
-    for v in range(8):
+    for v in range(11):
         sable.sable_plan_set_variant(p, 0, v)
         err = check_spmv(p, A, x)
         print(f"  variant {v}: {err:.2e}")
     y = torch.empty(A.nrows, device="cuda")
-    for v in range(10):
+    for v in range(13):
         sable.sable_plan_set_variant(p, 2, v)
         sable.sable_csr_spmv(p, xd, y)
         torch.cuda.synchronize()
