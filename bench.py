@@ -100,6 +100,29 @@ def cpu_baseline_spmm(A, X, rows=20000, target_s=10.0):
             "sample": f"FP64 SpMM (n={n}) of the first {sel.size} rows, {passes} passes ({dt:.1f} s)"}
 
 
+def variant_kernel(v: int) -> str:
+    if v <= 2:
+        return f"k_spmv_stream<{1 << v}, false>"
+    if v >= 8:
+        return f"k_spmv_stream<{1 << (v - 8)}, true>"
+    return f"k_spmv_fused<{1 << (v - 3)}>"
+
+
+def measured_traffic(name: str, kernel: str):
+    """Counter-based bytes per launch from profiles/<name>_traffic.json, only if they were
+    taken for this kernel with the current kernel source (else None)."""
+    from paper_2407_00829_amd import profsum
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    if rec.get("kernel") != kernel or rec.get("kernel_source_sha256") != profsum.kernel_source_sha():
+        return None
+    return rec["traffic_bytes"]
+
+
 def run_spmv(args, torch, sable, synth, oracle):
     if args.workload == "c2":
         log("[bench] generating PDE-like matrix (2,097,152 rows)")
@@ -157,7 +180,8 @@ def run_spmv(args, torch, sable, synth, oracle):
                    "vbr_tile": info["vbr_tile"], "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_spmv_fused", "bytes_per_launch": bytes_h,
+                     "traffic": measured_traffic(f"spmv_{args.workload}", variant_kernel(info["spmv_variant"])),
+                     "kernel": variant_kernel(info["spmv_variant"]), "bytes_per_launch": bytes_h,
                      "launch_ms": round(ev_ms, 5)},
         "rel_err_fp64": err,
         "plain_csr": {"gflops": round(2.0 * nnz / (wall_p / args.steps) / 1e9, 2),
@@ -220,11 +244,12 @@ def run_spmm(args, torch, sable, synth, oracle):
 
 
 def run_copy(args, torch):
-    """Plain device copy of 1 GiB: the reference for scaling HBM byte counters."""
+    """Plain elementwise device copy (1 GiB read, 1 GiB written): the reference for scaling
+    HBM byte counters."""
     a = torch.empty(256 * 1024 * 1024, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
-    f = lambda: b.copy_(a)  # noqa: E731
+    f = lambda: torch.mul(a, 1.0, out=b)  # noqa: E731
     wall, ev_ms = timed_steps(f, args.steps, args.warmup, torch)
     nbytes = 2 * a.numel() * 4
     return {"workload": "copy", "bytes_per_launch": nbytes, "launch_ms": ev_ms,

@@ -125,6 +125,7 @@ void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list
     build_schedule(P, P.sched[k], 256 << k, true, s);
     build_schedule(P, P.sched_plain[k], 256 << k, false, s);
   }
+  build_schedule(P, P.sched_mm, 64, true, s);
   HIPC(hipStreamSynchronize(s));
   P.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -155,8 +156,8 @@ sable::i64 sable_plan_s::device_bytes() const {
   b += blk.bytes() + blk_val_ptr.bytes() + vbr_val.bytes() + vbr_hi.bytes() + vbr_lo.bytes();
   b += csr_ptr.bytes() + csr_col.bytes() + csr_val.bytes();
   b += a_ptr.bytes() + a_col.bytes() + a_val.bytes() + owner.bytes() + slot.bytes();
-  for (int k = 0; k < 6; ++k) {
-    const sable::Schedule* S = k < 3 ? &sched[k] : &sched_plain[k - 3];
+  for (int k = 0; k < 7; ++k) {
+    const sable::Schedule* S = k < 3 ? &sched[k] : k < 6 ? &sched_plain[k - 3] : &sched_mm;
     b += S->tile_seg_lo.bytes() + S->tile_seg_hi.bytes() + S->tile_blk_ptr.bytes() +
          S->tile_blk.bytes();
   }

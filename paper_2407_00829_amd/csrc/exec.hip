@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_spmv_plain(const int32_t* __restrict__ 
 
 __global__ __launch_bounds__(kMmThreads) void k_spmm_tile(PlanView P, const float* __restrict__ X,
                                                          float* __restrict__ Y, int n, int use_mfma) {
-  __shared__ float ys[kMmRows * kMmCols];
+  __shared__ float ys[kMmRows * kMmCols + kMmBlkStage * 6];
   const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
   const int t = xcd_tile(blockIdx.x, ntile);
   if (t >= ntile) return;
@@ -313,7 +313,7 @@ void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStrea
 }
 
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s) {
-  const PlanView v = make_view(P, P.sched[0], false);
+  const PlanView v = make_view(P, P.prm.spmm_mode == 2 ? P.sched[0] : P.sched_mm, false);
   const int mode = P.prm.spmm_mode;
   if (mode == 2) {
     const unsigned nb = (unsigned)((P.nrows + 3) / 4);

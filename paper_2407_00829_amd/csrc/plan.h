@@ -72,6 +72,7 @@ struct sable_plan_s {
   // schedule and tuned parameters
   sable::Schedule sched[3];        // tiles of 256, 512, 1024 rows with the formats
   sable::Schedule sched_plain[3];  // the same tilings for the whole input as CSR
+  sable::Schedule sched_mm;        // 64-row tiles of the fused SpMM
   sable::ExecParams prm;
   uint32_t flags = 0;
   double plan_ms = 0.0;

@@ -3,13 +3,17 @@
 // A workgroup (4 waves) owns kMmRows output rows and up to kMmCols columns of Y, held in LDS.
 //  1. bands (VALU fp32): lanes across columns, one row per lane group; each cell's value is
 //     broadcast and multiplied with a coalesced row of X;
-//  2. blocks (matrix cores): every block overlapping the tile is a dense (rows x w) operand.
-//     With bf16 copies present, each 16x16x16 step runs three bf16 products with fp32
-//     accumulation, hi*hi + hi*lo + lo*hi (a = hi + lo split of the fp32 values, X split on
-//     the fly), i.e. split-precision products that keep ~16 significant bits per operand.
-//     Wave w owns the 16-column chunks w, w+4, ... so each Y element is updated by one lane
-//     in block order. Without bf16 copies blocks run in fp32 on the VALU.
-//  3. CSR (VALU fp32) accumulated separately, then Y = (bands + blocks) + CSR is stored.
+//  2. blocks (matrix cores): every block overlapping the tile is a dense (rows x w) operand,
+//     zero-padded to 16-row slices and 16-wide k steps. With bf16 copies present, each
+//     16x16x16 step runs three bf16 products with fp32 accumulation, hi*hi + hi*lo + lo*hi
+//     (a = hi + lo split of the fp32 values, X split on the fly), i.e. split-precision
+//     products that keep ~16 significant bits per operand. Wave w owns the 16-column chunks
+//     w and w+4 and keeps their accumulators for all four row slices in registers across all
+//     blocks (block order), so there is no synchronisation between blocks and each X
+//     fragment serves every row slice; the sums are then added to the band partial.
+//     Without bf16 copies blocks run in fp32 on the VALU.
+//  3. CSR (VALU fp32, eight X rows in flight per lane) accumulated separately, then
+//     Y = (bands + blocks) + CSR is stored.
 // Every element has a fixed summation order, so results are bitwise reproducible.
 #pragma once
 
@@ -20,6 +24,7 @@ namespace sable {
 constexpr int kMmRows = 64;
 constexpr int kMmCols = 128;
 constexpr int kMmThreads = 256;
+constexpr int kMmBlkStage = 256;  // block descriptors staged in LDS per pass
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
@@ -33,11 +38,29 @@ __device__ __forceinline__ uint16_t bf16_rne_dev(float f) {
 
 __device__ __forceinline__ float bf16_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// Rows [r0, r0+kMmRows) x columns [cb, cb+nc) of Y; ys = LDS (kMmRows x kMmCols floats).
-// tile256 = index of the 256-row schedule tile containing r0 (its lists are a superset).
+// Copy nq block descriptors of the tile list (starting at q0) into LDS, all threads.
+__device__ __forceinline__ void stage_blocks(const PlanView& P, int q0, int nq, int* sb) {
+  __syncthreads();  // the previous pass is done with sb
+  for (int j = threadIdx.x; j < nq; j += blockDim.x) {
+    const int b = P.tile_blk[q0 + j];
+    const i64 vp = P.blk_val_ptr[b];
+    sb[6 * j] = P.blk[4 * b];
+    sb[6 * j + 1] = P.blk[4 * b + 1];
+    sb[6 * j + 2] = P.blk[4 * b + 2];
+    sb[6 * j + 3] = P.blk[4 * b + 3];
+    sb[6 * j + 4] = (int)(uint32_t)((uint64_t)vp & 0xffffffffu);
+    sb[6 * j + 5] = (int)(uint32_t)((uint64_t)vp >> 32);
+  }
+  __syncthreads();
+}
+
+// Rows [r0, r0+kMmRows) x columns [cb, cb+nc) of Y. lds = kMmRows x kMmCols floats for the
+// tile of Y, then kMmBlkStage block descriptors (r0, r1, c0, c1, value offset). The view's
+// schedule has tiles of kMmRows rows, so tile lists hold exactly the overlapping blocks.
 __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int n,
                                           const float* __restrict__ X, float* __restrict__ Y,
                                           float* __restrict__ ys, bool use_mfma) {
+  int* sb = reinterpret_cast<int*>(ys + kMmRows * kMmCols);  // [kMmBlkStage][6]
   const int nc = min(kMmCols, n - cb);
   const int rend = min(r0 + kMmRows, P.nrows);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -78,25 +101,49 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
 
   // 2. blocks
   const int blo = P.tile_blk_ptr[tile], bhi = P.tile_blk_ptr[tile + 1];
-  for (int qb = blo; qb < bhi; ++qb) {
-    const int b = P.tile_blk[qb];
-    const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
-    const int lo = max(br0, r0), hi = min(br1, rend);
-    if (lo >= hi) continue;
-    const int c0 = P.blk[4 * b + 2], c1 = P.blk[4 * b + 3];
-    const int h = br1 - br0, w = c1 - c0;
-    const i64 vp = P.blk_val_ptr[b];
-    if (use_mfma) {
-      const int m = lane & 15, kg = lane >> 4;  // MFMA operand coordinates of this lane
-      for (int nch = wave; nch * 16 < nc; nch += 4) {
-        const int col = nch * 16 + m;  // B / D column within the chunk
+  if (use_mfma) {
+    // Wave w owns the 16-column chunks w and w+4 of this column block and all four 16-row
+    // slices of the tile; products accumulate in registers over the tile's blocks in block
+    // order, then are added to the band partial in LDS.
+    floatx4_t acc[4][2];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int ci = 0; ci < 2; ++ci) acc[mt][ci] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    const int m = lane & 15, kg = lane >> 4;  // MFMA operand coordinates of this lane
+    for (int q0 = blo; q0 < bhi; q0 += kMmBlkStage) {
+     const int nq = min(kMmBlkStage, bhi - q0);
+     stage_blocks(P, q0, nq, sb);
+     for (int j = 0; j < nq; ++j) {
+      const int br0 = sb[6 * j], br1 = sb[6 * j + 1];
+      const int lo = max(br0, r0), hi = min(br1, rend);
+      if (lo >= hi) continue;
+      const int c0 = sb[6 * j + 2], c1 = sb[6 * j + 3];
+      const int h = br1 - br0, w = c1 - c0;
+      const i64 vp = (i64)(((uint64_t)(uint32_t)sb[6 * j + 5] << 32) | (uint32_t)sb[6 * j + 4]);
+#pragma unroll
+      for (int ci = 0; ci < 2; ++ci) {
+        const int nch = wave + 4 * ci;
+        if (nch * 16 >= nc) continue;
+        const int col = nch * 16 + m;
         const bool cok = col < nc;
-        for (int mt = lo; mt < hi; mt += 16) {
-          floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
-          const int arow = mt + m;  // A row of this lane
-          const bool rok = arow < hi;
-          for (int k0 = 0; k0 < w; k0 += 16) {
-            bf16x4_t ahi, alo, bhi, blo2;
+        for (int k0 = 0; k0 < w; k0 += 16) {
+          bf16x4_t bh, bl;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int k = k0 + 4 * kg + i;
+            const float xv = (cok && k < w) ? X[(i64)(c0 + k) * n + cb + col] : 0.f;
+            const uint16_t xh = bf16_rne_dev(xv);
+            bh[i] = (short)xh;
+            bl[i] = (short)bf16_rne_dev(xv - bf16_f32(xh));
+          }
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) {
+            const int m0 = r0 + 16 * mt;
+            if (m0 >= hi || m0 + 16 <= lo) continue;
+            const int arow = m0 + m;
+            const bool rok = arow >= lo && arow < hi;
+            bf16x4_t ah, al;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int k = k0 + 4 * kg + i;
@@ -106,27 +153,40 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
                 h16 = P.vbr_hi[at];
                 l16 = P.vbr_lo[at];
               }
-              ahi[i] = (short)h16;
-              alo[i] = (short)l16;
-              float xv = 0.f;
-              if (cok && k < w) xv = X[(i64)(c0 + k) * n + cb + col];
-              const uint16_t xh = bf16_rne_dev(xv);
-              const uint16_t xl = bf16_rne_dev(xv - bf16_f32(xh));
-              bhi[i] = (short)xh;
-              blo2[i] = (short)xl;
+              ah[i] = (short)h16;
+              al[i] = (short)l16;
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo2, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int orow = mt + 4 * kg + i;  // D row of this lane
-            if (orow < hi && cok) ys[(orow - r0) * kMmCols + col] += acc[i];
+            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[mt][ci], 0, 0, 0);
+            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[mt][ci], 0, 0, 0);
+            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[mt][ci], 0, 0, 0);
           }
         }
       }
-    } else {
+     }
+    }
+    if (blo < bhi) {
+#pragma unroll
+      for (int ci = 0; ci < 2; ++ci) {
+        const int col = (wave + 4 * ci) * 16 + m;
+        if (col >= nc) continue;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) ys[(16 * mt + 4 * kg + i) * kMmCols + col] += acc[mt][ci][i];
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int q0 = blo; q0 < bhi; q0 += kMmBlkStage) {
+     const int nq = min(kMmBlkStage, bhi - q0);
+     stage_blocks(P, q0, nq, sb);
+     for (int j = 0; j < nq; ++j) {
+      const int br0 = sb[6 * j], br1 = sb[6 * j + 1];
+      const int lo = max(br0, r0), hi = min(br1, rend);
+      if (lo >= hi) continue;
+      const int c0 = sb[6 * j + 2], c1 = sb[6 * j + 3];
+      const int h = br1 - br0, w = c1 - c0;
+      const i64 vp = (i64)(((uint64_t)(uint32_t)sb[6 * j + 5] << 32) | (uint32_t)sb[6 * j + 4]);
       for (int rl = wave * rpw + sub; rl < kMmRows; rl += 4 * rpw) {
         const int r = r0 + rl;
         if (r < lo || r >= hi) continue;
@@ -141,6 +201,7 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
         if (okA) ys[rl * kMmCols + cA] += a0;
         if (okB) ys[rl * kMmCols + cB] += a1;
       }
+     }
     }
     __syncthreads();
   }
@@ -152,12 +213,21 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
     float a0 = 0.f, a1 = 0.f;
     const int ke = P.csr_ptr[r + 1];
     int k = P.csr_ptr[r];
-    for (; k + 2 <= ke; k += 2) {
-      const float v0 = P.csr_val[k], v1 = P.csr_val[k + 1];
-      const float* x0 = X + (i64)P.csr_col[k] * n + cb;
-      const float* x1 = X + (i64)P.csr_col[k + 1] * n + cb;
-      if (okA) { a0 += v0 * x0[cA]; a0 += v1 * x1[cA]; }
-      if (okB) { a1 += v0 * x0[cB]; a1 += v1 * x1[cB]; }
+    // eight X rows in flight per lane
+    for (; k + 8 <= ke; k += 8) {
+      float va[8], xa[8], xb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        va[u] = P.csr_val[k + u];
+        const float* xr = X + (i64)P.csr_col[k + u] * n + cb;
+        xa[u] = okA ? xr[cA] : 0.f;
+        xb[u] = okB ? xr[cB] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a0 += va[u] * xa[u];
+        a1 += va[u] * xb[u];
+      }
     }
     for (; k < ke; ++k) {
       const float v0 = P.csr_val[k];

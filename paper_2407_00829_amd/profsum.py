@@ -1,0 +1,115 @@
+"""Summaries of rocprofv3 CSV output for profiles/: kernel durations and HBM bytes.
+
+    python -m paper_2407_00829_amd.profsum --name spmv_c2 --kernel "k_spmv_stream<1, false>" \
+        --trace DIR --fetch DIR --write DIR --fetch-copy DIR --write-copy DIR \
+        --copy-bytes 1073741824 --cmd "<profiled command>"
+
+Writes profiles/<name>.md (the figures and the commands) and profiles/<name>_traffic.json
+(per-launch fetched / written bytes of the kernel, scaled by the copy calibration, and the
+SHA-256 of the SpMV kernel source the counters were taken with).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", "exec.h")]
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _csv(d, suffix):
+    files = glob.glob(os.path.join(d, f"*{suffix}"))
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def kernel_stats(trace_dir):
+    return _csv(trace_dir, "kernel_stats.csv")
+
+
+def counter_mean_kib(d, kernel):
+    vals = [float(r["Counter_Value"]) for r in _csv(d, "counter_collection.csv")
+            if kernel in r["Kernel_Name"]]
+    if not vals:
+        raise ValueError(f"kernel {kernel!r} not found under {d}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--copy-kernel", default="elementwise")
+    ap.add_argument("--copy-bytes", type=float, default=2 * 1024 ** 3)
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch-copy", required=True)
+    ap.add_argument("--write-copy", required=True)
+    ap.add_argument("--cmd", required=True)
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    a = ap.parse_args(argv)
+    rows = kernel_stats(a.trace)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    f_k, nf = counter_mean_kib(a.fetch, a.kernel)
+    w_k, nw = counter_mean_kib(a.write, a.kernel)
+    fc, _ = counter_mean_kib(a.fetch_copy, a.copy_kernel)
+    wc, _ = counter_mean_kib(a.write_copy, a.copy_kernel)
+    half = a.copy_bytes / 2  # the copy reads half and writes half of copy_bytes
+    ff = half / (fc * 1024.0)
+    wf = half / (wc * 1024.0)
+    fetch_b = f_k * 1024.0 * ff
+    write_b = w_k * 1024.0 * wf
+    sel = [r for r in rows if a.kernel in r["Name"]]
+    md = [f"# {a.name}: rocprofv3 kernel trace and HBM counters", "",
+          "Commands (run from /tmp with TMPDIR=/tmp; DIR is an output directory):", "",
+          f"    rocprofv3 --kernel-trace --stats --output-format csv -d DIR -o run -- {a.cmd}",
+          f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o run -- {a.cmd}",
+          f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR -o run -- {a.cmd}",
+          "    rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE --output-format csv -d DIR -o copy -- "
+          "python3 bench.py --workload copy --steps 10 --warmup 2", "",
+          "## Kernel durations (kernel-trace stats, top 12 by total time)", "",
+          "| kernel | calls | average us | min us | max us |", "|---|---|---|---|---|"]
+    for r in rows[:12]:
+        md.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                  f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
+    md += ["", f"## HBM bytes of `{a.kernel}`", "",
+           f"* FETCH_SIZE mean {f_k:.1f} KiB per dispatch over {nf} dispatches; WRITE_SIZE "
+           f"{w_k:.1f} KiB over {nw}.",
+           f"* Calibration with a plain device copy of {a.copy_bytes / 2 ** 30:.2f} GiB "
+           f"(half read, half written): FETCH_SIZE reads {fc:.0f} KiB -> factor {ff:.3f}; "
+           f"WRITE_SIZE reads {wc:.0f} KiB -> factor {wf:.3f}.",
+           f"* Traffic per launch: fetched {fetch_b / 1e6:.1f} MB + written {write_b / 1e6:.1f} MB "
+           f"= {(fetch_b + write_b) / 1e6:.1f} MB."]
+    if sel:
+        avg = float(sel[0]["AverageNs"]) / 1e3
+        md.append(f"* Average duration {avg:.2f} us -> {(fetch_b + write_b) / (avg * 1e-6) / 1e12:.2f} "
+                  "TB/s of counted traffic.")
+    os.makedirs(a.out, exist_ok=True)
+    with open(os.path.join(a.out, f"{a.name}.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    rec = {"kernel": a.kernel, "fetch_kib": f_k, "write_kib": w_k, "fetch_factor": ff,
+           "write_factor": wf, "traffic_bytes": fetch_b + write_b,
+           "kernel_source_sha256": kernel_source_sha(), "command": a.cmd}
+    with open(os.path.join(a.out, f"{a.name}_traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    print("\n".join(md))
+
+
+if __name__ == "__main__":
+    main()
