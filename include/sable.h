@@ -82,7 +82,8 @@ typedef struct {
  *   amin_band       minimum total area of an accepted band region (Alg. 3, default 2500)
  *   lseg            minimum segment length l_seg (Alg. 4; default 64) - also the count
  *                   threshold for candidate diagonals (Alg. 3)
- *   wmax            cap on ribbon extent below / above the candidate diagonal (default 32)
+ *   wmax            cap on ribbon extent below / above the candidate diagonal (default 32,
+ *                   at most 63)
  *   dmax            largest |offset| considered (Alg. 3; -1 = all)
  *   coverage_pm     block coverage cutoff (Alg. 1; default 80 = 8%)
  *   tile_set_mask   tiled search: bit t selects tile size {4,6,8,16,32}[t]; 0 = all

@@ -219,7 +219,7 @@ sable_status sable_plan(const sable_csr* A, const sable_extractor* list, int32_t
     if (th_in) th = *th_in;
     if (th.delta_block_pm < 500 || th.delta_block_pm > 1000 || th.delta_band_pm < 1 ||
         th.delta_band_pm > 1000 || th.amin_block < 1 || th.amin_band < 1 || th.lseg < 1 ||
-        th.wmax < 0 || th.coverage_pm < 0 || th.coverage_pm > 1000 || th.tile_set_mask < 0 ||
+        th.wmax < 0 || th.wmax > 63 || th.coverage_pm < 0 || th.coverage_pm > 1000 || th.tile_set_mask < 0 ||
         th.tile_set_mask > 31)
       SB_THROW(SABLE_ERR_INVALID_ARG, "threshold out of range");
     hipStream_t s = (hipStream_t)stream;

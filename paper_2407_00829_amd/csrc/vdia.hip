@@ -7,8 +7,9 @@
 //   2. Candidates: diagonals with M[d] >= l_seg (count threshold), ranked by M descending,
 //      then d ascending, with a 64-bit key radix sort.
 //   3. Candidates are processed in order, in speculative batches: FitRibbon runs one thread
-//      per (candidate, present row); GrowSegments runs one wave per candidate, 64 rows per
-//      step with wave scans. A candidate reads only the rows on its diagonal (their used
+//      per (candidate, present row) and also records which offsets within W_max of the
+//      diagonal are present (two 64-bit masks); GrowSegments runs one wave per candidate,
+//      64 rows per step with wave scans and mask popcounts. A candidate reads only the rows on its diagonal (their used
 //      flag and their own entries), so its result is exact unless a candidate accepted
 //      earlier in the same batch claimed one of those rows; the host checks this with row
 //      spans and re-runs the batch from the first conflicting candidate.
@@ -64,7 +65,8 @@ __global__ void k_fit_ribbon(const int32_t* __restrict__ bpre, int nb, const i64
                              const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
                              const uint8_t* __restrict__ used, int p, int wmax,
                              int32_t* __restrict__ Lp, int32_t* __restrict__ Up,
-                             int32_t* __restrict__ Kp) {
+                             int32_t* __restrict__ Kp, uint64_t* __restrict__ Mlo,
+                             uint64_t* __restrict__ Mhi) {
   for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < items; t += (i64)gridDim.x * blockDim.x) {
     int lo = 0, hi = nb - 1;  // last c with bpre[c] <= t
     while (lo < hi) {
@@ -109,6 +111,24 @@ __global__ void k_fit_ribbon(const int32_t* __restrict__ bpre, int nb, const i64
     Lp[pos] = l;
     Up[pos] = u;
     Kp[pos] = k;
+    // presence masks around the centre: bit t of lo = offset d-1-t, bit t of hi = offset d+t
+    uint64_t mlo = 0, mhi = 0;
+    if (k) {
+      const int d = cd[c];
+      const int rs = rptr[i], re = rptr[i + 1];
+      for (int q = e; q < re; ++q) {
+        const int t = rcol[q] - (i + d);
+        if (t > wmax) break;
+        mhi |= 1ull << t;
+      }
+      for (int q = e - 1; q >= rs; --q) {
+        const int t = (i + d) - 1 - rcol[q];
+        if (t >= wmax) break;
+        mlo |= 1ull << t;
+      }
+    }
+    Mlo[pos] = mlo;
+    Mhi[pos] = mhi;
   }
 }
 
@@ -147,32 +167,33 @@ __device__ inline int wave_incl_max(int v, int lane) {
 
 __device__ inline int first_lane(unsigned long long m) { return m ? __ffsll((long long)m) - 1 : 64; }
 
-// Present cells of row srow[pos] in offsets [d-L, d+U], walking out from the centre entry.
-__device__ inline int count_window(i64 pos, int d, int L, int U, const int32_t* __restrict__ perm,
-                                   const int32_t* __restrict__ srow, const int32_t* __restrict__ rptr,
-                                   const int32_t* __restrict__ rcol) {
-  const int r = srow[pos], e = perm[pos];
-  const int rs = rptr[r], re = rptr[r + 1];
-  const int clo = r + d - L, chi = r + d + U;
-  int n = 1;
-  for (int q = e - 1; q >= rs && rcol[q] >= clo; --q) ++n;
-  for (int q = e + 1; q < re && rcol[q] <= chi; ++q) ++n;
-  return n;
-}
-
 struct CandStat {
   i64 area, z;
   int32_t nseg, rmin, rmax, first_row, last_row, pad;
 };
 
-// GrowSegments (Alg. 4), one 64-lane wave per candidate diagonal.
+// Present cells of a row in offsets [d-L, d+U] from its presence masks (L <= 64, U <= 63).
+__device__ __forceinline__ int mask_count(uint64_t mlo, uint64_t mhi, int L, int U) {
+  const uint64_t ml = L >= 64 ? ~0ull : ((1ull << L) - 1ull);
+  const uint64_t mh = U >= 63 ? ~0ull : ((1ull << (U + 1)) - 1ull);
+  return __popcll(mlo & ml) + __popcll(mhi & mh);
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  return (uint64_t)shfl64((i64)v, src);
+}
+
+// GrowSegments (Alg. 4), one 64-lane wave per candidate diagonal. Lanes hold 64 consecutive
+// positions of the candidate's row list (64 consecutive rows while the run lasts); window
+// counts come from presence masks, so a segment that breaks inside a chunk restarts at the
+// breaking lane without reloading anything.
 __global__ __launch_bounds__(64) void k_grow(
     int nb, const i64* __restrict__ cstart, const int32_t* __restrict__ ccnt,
-    const int32_t* __restrict__ cd, const int32_t* __restrict__ perm,
-    const int32_t* __restrict__ srow, const int32_t* __restrict__ rptr,
-    const int32_t* __restrict__ rcol, const int32_t* __restrict__ Lp,
-    const int32_t* __restrict__ Up, const int32_t* __restrict__ Kp, int nrows, int p, int lseg,
-    SegRec* __restrict__ segs, int* __restrict__ nsegs, int seg_cap, CandStat* __restrict__ stat) {
+    const int32_t* __restrict__ cd, const int32_t* __restrict__ srow,
+    const int32_t* __restrict__ Lp, const int32_t* __restrict__ Up,
+    const int32_t* __restrict__ Kp, const uint64_t* __restrict__ Mlo,
+    const uint64_t* __restrict__ Mhi, int nrows, int p, int lseg, SegRec* __restrict__ segs,
+    int* __restrict__ nsegs, int seg_cap, CandStat* __restrict__ stat) {
   const int c = blockIdx.x;
   if (c >= nb) return;
   const int lane = threadIdx.x;
@@ -201,7 +222,7 @@ __global__ __launch_bounds__(64) void k_grow(
 
   int q = 0;
   while (q < cnt) {
-    // next position with k > 0
+    // next position with k > 0 starts a segment
     bool found = false;
     while (q < cnt) {
       const int pq = q + lane;
@@ -211,60 +232,83 @@ __global__ __launch_bounds__(64) void k_grow(
       q += 64;
     }
     if (!found) break;
-    const int qs = q;
-    const int i0 = srow[st + qs];
+    int qs = q;                      // position of the current segment's first row
+    const int row0_first = srow[st + qs];
+    int i0 = row0_first;
     int L = Lp[st + qs], U = Up[st + qs];
-    i64 z = count_window(st + qs, d, L, U, perm, srow, rptr, rcol);
-    int qj = qs + 1, j = i0 + 1;
-    for (;;) {
-      const int pq = qj + lane;
-      const bool valid = pq < cnt && j + lane < nrows && srow[st + (pq < cnt ? pq : 0)] == j + lane &&
-                         Kp[st + (pq < cnt ? pq : 0)] > 0;
-      const int f = first_lane(__ballot(!valid));
-      const int lv = lane < f ? Lp[st + pq] : 0;
-      const int uv = lane < f ? Up[st + pq] : 0;
-      const int Lm = max(L, wave_incl_max(lv, lane));
-      const int Um = max(U, wave_incl_max(uv, lane));
-      const bool widen = lane < f && (Lm != L || Um != U);
-      const int w = first_lane(__ballot(widen));
-      const int lim = min(f, w);
-      const i64 cv = lane < lim ? count_window(st + pq, d, L, U, perm, srow, rptr, rcol) : 0;
-      const i64 zp = z + wave_incl_sum(cv, lane);
-      const i64 area = (i64)(L + U + 1) * (j + lane - i0 + 1);
-      const bool brk = lane < lim && 1000LL * zp < (long long)p * area;
-      const int b = first_lane(__ballot(brk));
-      if (b < lim) {
-        const i64 zb = b > 0 ? shfl64(zp, b - 1) : z;
-        emit(i0, j + b, L, U, zb);
-        q = qj + b;
-        break;
-      }
-      if (w < f) {
-        z = w > 0 ? shfl64(zp, w - 1) : z;
-        j += w;
-        qj += w;
-        const int L2 = __shfl(Lm, w, 64), U2 = __shfl(Um, w, 64);
-        i64 part = 0;
-        for (int pp = qs + lane; pp <= qj; pp += 64)
-          part += count_window(st + pp, d, L2, U2, perm, srow, rptr, rcol);
-        const i64 z2 = wave_sum(part);
-        const i64 area2 = (i64)(L2 + U2 + 1) * (j - i0 + 1);
-        if (1000LL * z2 < (long long)p * area2) {
-          emit(i0, j, L, U, z);
-          q = qj;
-          break;
+    i64 z = Kp[st + qs];
+    int cpos = qs;                   // position held by lane 0 of the current chunk
+    int row0 = row0_first;           // row of lane 0 when the run continues
+    int base = 1;                    // first lane still to examine
+    bool done = false;
+    while (!done) {
+      const int pq = cpos + lane;
+      const int pc = pq < cnt ? pq : cnt - 1;
+      const bool valid = pq < cnt && row0 + lane < nrows && srow[st + pc] == row0 + lane &&
+                         Kp[st + pc] > 0;
+      const int lv = valid ? Lp[st + pc] : 0, uv = valid ? Up[st + pc] : 0;
+      const int kv = valid ? Kp[st + pc] : 0;
+      const uint64_t mlo = valid ? Mlo[st + pc] : 0ull, mhi = valid ? Mhi[st + pc] : 0ull;
+      const unsigned long long inval = __ballot(!valid);
+      while (base < 64) {
+        const unsigned long long above = ~0ull << base;
+        const int f = first_lane(inval & above);   // first invalid lane at or after base
+        const int Lm = max(L, wave_incl_max(lane >= base ? lv : 0, lane));
+        const int Um = max(U, wave_incl_max(lane >= base ? uv : 0, lane));
+        const bool widen = lane >= base && lane < f && (Lm != L || Um != U);
+        const int w = first_lane(__ballot(widen));
+        const int lim = min(f, w);
+        const i64 cv = (lane >= base && lane < lim) ? mask_count(mlo, mhi, L, U) : 0;
+        const i64 zp = z + wave_incl_sum(cv, lane);
+        const i64 area = (i64)(L + U + 1) * (row0 + lane - i0 + 1);
+        const bool brk = lane >= base && lane < lim && 1000LL * zp < (long long)p * area;
+        const int b = first_lane(__ballot(brk));
+        if (b < lim) {
+          emit(i0, row0 + b, L, U, b > base ? shfl64(zp, b - 1) : z);
+          i0 = row0 + b;
+          L = __shfl(lv, b, 64);
+          U = __shfl(uv, b, 64);
+          z = __shfl(kv, b, 64);
+          qs = cpos + b;
+          base = b + 1;
+          continue;
         }
-        L = L2; U = U2; z = z2;
-        ++j; ++qj;
-        continue;
+        if (w < f) {
+          z = w > base ? shfl64(zp, w - 1) : z;
+          const int L2 = __shfl(Lm, w, 64), U2 = __shfl(Um, w, 64);
+          // exact recount over the segment's rows with the widened extents
+          i64 part = 0;
+          for (int pp = qs + lane; pp < cpos; pp += 64)
+            part += mask_count(Mlo[st + pp], Mhi[st + pp], L2, U2);
+          const int from = max(qs - cpos, 0);
+          if (lane >= from && lane <= w) part += mask_count(mlo, mhi, L2, U2);
+          const i64 z2 = wave_sum(part);
+          const i64 area2 = (i64)(L2 + U2 + 1) * (row0 + w - i0 + 1);
+          if (1000LL * z2 < (long long)p * area2) {
+            emit(i0, row0 + w, L, U, z);
+            i0 = row0 + w;
+            L = __shfl(lv, w, 64);
+            U = __shfl(uv, w, 64);
+            z = __shfl(kv, w, 64);
+            qs = cpos + w;
+          } else {
+            L = L2; U = U2; z = z2;
+          }
+          base = w + 1;
+          continue;
+        }
+        z = f > base ? shfl64(zp, f - 1) : z;
+        if (f < 64) {  // the run of k > 0 rows ends before lane f
+          emit(i0, row0 + f, L, U, z);
+          q = cpos + f;
+          done = true;
+        }
+        base = 64;
       }
-      z = f > 0 ? shfl64(zp, f - 1) : z;
-      j += f;
-      qj += f;
-      if (f < 64) {
-        emit(i0, j, L, U, z);
-        q = qj;
-        break;
+      if (!done) {
+        cpos += 64;
+        row0 += 64;
+        base = 0;
       }
     }
   }
@@ -369,6 +413,7 @@ void extract_bands(sable_plan_s& P, const Resid& R, const sable_thresholds& th,
     DBuf<uint8_t> used(n);
     HIPC(hipMemsetAsync(used.p, 0, n, s));
     DBuf<int32_t> Lp(R.nnz), Up(R.nnz), Kp(R.nnz);
+    DBuf<uint64_t> Mlo(R.nnz), Mhi(R.nnz);
     int b0 = 0, bsize = 1;
     const i64 item_budget = (i64)1 << 26;
     while (b0 < ncand) {
@@ -398,15 +443,14 @@ void extract_bands(sable_plan_s& P, const Resid& R, const sable_thresholds& th,
       to_dev(d_bd, bd, s);
       k_fit_ribbon<<<grid_for(items, 256), 256, 0, s>>>(d_bpre.p, nb, d_bst.p, d_bd.p, items,
                                                         perm.p, srow.p, R.ptr.p, R.col.p, used.p,
-                                                        p, th.wmax, Lp.p, Up.p, Kp.p);
+                                                        p, th.wmax, Lp.p, Up.p, Kp.p, Mlo.p, Mhi.p);
       LAUNCH_CHECK();
       DBuf<SegRec> segs(seg_cap);
       DBuf<int> nsegs(1);
       DBuf<CandStat> stat(nb);
       HIPC(hipMemsetAsync(nsegs.p, 0, sizeof(int), s));
-      k_grow<<<nb, 64, 0, s>>>(nb, d_bst.p, d_bcnt.p, d_bd.p, perm.p, srow.p, R.ptr.p, R.col.p,
-                               Lp.p, Up.p, Kp.p, n, p, th.lseg, segs.p, nsegs.p, (int)seg_cap,
-                               stat.p);
+      k_grow<<<nb, 64, 0, s>>>(nb, d_bst.p, d_bcnt.p, d_bd.p, srow.p, Lp.p, Up.p, Kp.p, Mlo.p,
+                               Mhi.p, n, p, th.lseg, segs.p, nsegs.p, (int)seg_cap, stat.p);
       LAUNCH_CHECK();
       std::vector<CandStat> hs;
       to_host(hs, stat.p, nb, s);

@@ -77,7 +77,7 @@ def _diag_cells(n_rows: int, n_cols: int, d: int, start: int, length: int):
     return t + max(0, -d), t + max(0, d)
 
 
-def gen_c1(seed: int, n: int = 4096):
+def gen_c1(seed: int, n: int = 4096, scatter_count: int | None = None):
     """4096 x 4096 mixed matrix and x (both U(-1,1)).
 
     Draw order: for d in (0,-1,+1,+37): L ~ U{512..4096} clipped to n-|d|, start ~
@@ -103,7 +103,7 @@ def gen_c1(seed: int, n: int = 4096):
         rr, cc = np.meshgrid(np.arange(r0, r0 + h), np.arange(c0, c0 + w), indexing="ij")
         rs.append(rr.ravel())
         cs.append(cc.ravel())
-    k = int(round(0.0005 * n * n))
+    k = int(round(0.0005 * n * n)) if scatter_count is None else int(scatter_count)
     rs.append(rng.integers(0, n, k))
     cs.append(rng.integers(0, n, k))
     r = np.concatenate(rs)
@@ -329,6 +329,32 @@ def gen_random_small(seed: int, nrows: int, ncols: int, density: float,
     if v.size:
         v[rng.random(v.size) < 0.02] = 0.0
     return from_coo(nrows, ncols, r, c, v)
+
+
+def gen_c5_matrix(seed: int):
+    """One matrix of a serving batch: n ~ logU[1e3, 2e5]; generator kind uniform over
+    {C1-style, C2-style (grid g = round(n^(1/3))), C3-style, mixed}; op ~ Bernoulli(0.5)
+    (0 = SpMV, 1 = SpMM with 16 right-hand sides). Returns (A, kind, op)."""
+    rng = np.random.default_rng(7_000_003 + seed)
+    n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(2e5)))))
+    kind = int(rng.integers(0, 4))
+    op = int(rng.integers(0, 2))
+    sub = int(rng.integers(0, 2 ** 31 - 1))
+    if kind == 0:
+        m = max(n, 256)  # 0.05% of m^2 scattered entries, at most 4 per row
+        A, _ = gen_c1(sub, n=m, scatter_count=min(int(round(0.0005 * m * m)), 4 * m))
+    elif kind == 1:
+        g = max(8, int(round(n ** (1.0 / 3.0))))
+        bs = min(128, g * g)
+        A, _ = gen_c2(sub, g=g, nblocks=max(1, g * g * g // 32768), bs=bs)
+    elif kind == 2:
+        N = -(-n // 6)
+        ys = max(2, int(round(N ** (1.0 / 3.0))))
+        A, _ = gen_c3(sub, n=n, ystride=ys, zstride=ys * ys, scatter_density=min(1e-4, 20.0 / n),
+                      with_x=False)
+    else:
+        A, _ = gen_mixed(sub, n=n, rowlen=float(rng.uniform(4, 32)), pi=rng.dirichlet([1, 1, 1]))
+    return A, kind, op
 
 
 def gen_dense_vector(seed: int, n: int, normal: bool = False) -> np.ndarray:

@@ -242,3 +242,43 @@ def test_spmm_split_bf16_block_accuracy():
     sable.sable_plan_set_variant(p, 1, 0)
     err = check_spmm(p, A, 48, tol=2e-5)
     assert err > 1e-8  # the matrix-core path really ran in reduced precision
+
+
+def test_c1_full_paper_mode_against_stored_oracle():
+    """Full 4096^2 C1 under the literal block search: structure equal to the oracle's stored
+    result (tests/golden/c1_seed0_paper.txt, written by make_c1_paper.py from oracle/ only),
+    values checked entry by entry by the exact-cover invariants, product within 1e-5."""
+    from tests.conftest import read_golden
+    g = read_golden("c1_seed0_paper.txt")
+    A, x = synth.gen_c1(0)
+    th = oracle.Thresholds(amin_band=256, amin_block=256)
+    p = gpu_plan(A, [V, B, C], oracle.MODE_PAPER, th)
+    got = sable.sable_plan_export(p)
+    assert got["seg_row_start"].tolist() == g["seg_row_start"]
+    assert got["seg_nrows"].tolist() == g["seg_nrows"]
+    assert got["idiag"].tolist() == g["idiag"]
+    assert got["blk"].ravel().tolist() == g["blk"]
+    assert got["csr_col"].size == g["csr_nnz"][0]
+    oracle.check_partition(A, got, th, [V, B, C])
+    check_spmv(p, A, x)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_c2_full_size_sampled(seed):
+    """PDE-like 2,097,152-row matrix in the benchmark's configuration (autotuned kernel):
+    exact cover of every input entry, and sampled rows against the FP64 oracle."""
+    A, x = synth.gen_c2(seed)
+    th = oracle.Thresholds(delta_band_pm=750, delta_block_pm=500)
+    p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
+    xd = torch.from_numpy(x).cuda()
+    y = torch.empty(A.nrows, device="cuda")
+    sable.sable_autotune(p, 0, 1, xd, y)
+    got = sable.sable_plan_export(p)
+    oracle.check_partition(A, got, th, [V, B, C])
+    sable.sable_spmv(p, xd, y)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(seed).choice(A.nrows, 20000, replace=False)
+    rows = np.concatenate([rows, [0, A.nrows - 1]])
+    err = oracle.rel_err(y.cpu().numpy()[rows], oracle.spmv_rows(A, x, rows))
+    print(f"  sampled rel_err={err:.3e}")
+    assert err <= 1e-5
