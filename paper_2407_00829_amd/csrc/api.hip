@@ -153,7 +153,7 @@ sable::i64 sable_plan_s::device_bytes() const {
   sable::i64 b = 0;
   b += vdia_val.bytes() + idiag.bytes() + seg_row_start.bytes() + seg_nrows.bytes() +
        seg_ndiags.bytes() + seg_idiag_ptr.bytes() + seg_val_ptr.bytes();
-  b += blk.bytes() + blk_val_ptr.bytes() + vbr_val.bytes() + vbr_hi.bytes() + vbr_lo.bytes();
+  b += blk.bytes() + blk_val_ptr.bytes() + vbr_val.bytes() + vbr_mma.bytes() + blk_mma_ptr.bytes();
   b += csr_ptr.bytes() + csr_col.bytes() + csr_val.bytes();
   b += a_ptr.bytes() + a_col.bytes() + a_val.bytes() + owner.bytes() + slot.bytes();
   for (int k = 0; k < 7; ++k) {

@@ -31,7 +31,7 @@ __global__ void k_batch_reset(unsigned* __restrict__ counter, unsigned* __restri
   }
 }
 
-constexpr int kBatchLds = kMmRows * kMmCols + kMmBlkStage * 6;  // >= largest SpMV tile
+constexpr int kBatchLds = kMmRows * kMmCols + kMmBlkStage * kBlkDesc;  // >= largest SpMV tile
 static_assert(kBatchLds >= kCsrChunk + 1024, "LDS budget");
 
 __global__ __launch_bounds__(256) void k_batch(const PlanView* __restrict__ views,
@@ -142,7 +142,7 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
         hv[i] = make_view(P, P.sched_mm, false);
         d.units_per_col = (P.nrows + kMmRows - 1) / kMmRows;
         d.col_chunks = (it.n + kMmCols - 1) / kMmCols;
-        d.mfma = (P.prm.spmm_mode == 0 && P.vbr_hi.p && P.nblk > 0) ? 1 : 0;
+        d.mfma = (P.prm.spmm_mode == 0 && P.vbr_mma.p && P.nblk > 0) ? 1 : 0;
         units = (i64)d.units_per_col * d.col_chunks;
       }
       hi[i] = d;

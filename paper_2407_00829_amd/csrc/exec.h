@@ -19,8 +19,8 @@ struct PlanView {
   const int32_t* blk;
   const i64* blk_val_ptr;
   const float* vbr_val;
-  const uint16_t* vbr_hi;
-  const uint16_t* vbr_lo;
+  const uint32_t* vbr_mma;
+  const i64* blk_mma_ptr;
   const int32_t* csr_ptr;
   const int32_t* csr_col;
   const float* csr_val;

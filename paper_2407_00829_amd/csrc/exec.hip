@@ -35,8 +35,8 @@ PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain) {
   v.blk = P.blk.p;
   v.blk_val_ptr = P.blk_val_ptr.p;
   v.vbr_val = P.vbr_val.p;
-  v.vbr_hi = P.vbr_hi.p;
-  v.vbr_lo = P.vbr_lo.p;
+  v.vbr_mma = P.vbr_mma.p;
+  v.blk_mma_ptr = P.blk_mma_ptr.p;
   v.csr_ptr = P.csr_ptr.p;
   v.csr_col = P.csr_col.p;
   v.csr_val = P.csr_val.p;
@@ -102,13 +102,25 @@ __device__ inline uint16_t to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
-__global__ void k_split(const float* __restrict__ a, i64 n, uint16_t* __restrict__ hi,
-                        uint16_t* __restrict__ lo) {
-  for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x) {
-    const float v = a[k];
-    const uint16_t h = to_bf16_rne(v);
-    hi[k] = h;
-    lo[k] = to_bf16_rne(v - __uint_as_float((uint32_t)h << 16));
+// One workgroup per block: element (r, k) of the block (column-major in vbr_val) becomes the
+// word hi | lo << 16 at row-major position r * w4 + k; padding columns k >= w hold 0.
+__global__ void k_split_mma(const int32_t* __restrict__ blk, const i64* __restrict__ bvp,
+                            const i64* __restrict__ mptr, const float* __restrict__ val,
+                            uint32_t* __restrict__ out) {
+  const int b = blockIdx.x;
+  const int h = blk[4 * b + 1] - blk[4 * b], w = blk[4 * b + 3] - blk[4 * b + 2];
+  const int w4 = (w + 3) & ~3;
+  const i64 vp = bvp[b], mp = mptr[b];
+  for (i64 e = threadIdx.x; e < (i64)h * w4; e += blockDim.x) {
+    const int r = (int)(e / w4), k = (int)(e % w4);
+    uint32_t word = 0;
+    if (k < w) {
+      const float v = val[vp + (i64)k * h + r];
+      const uint16_t hi = to_bf16_rne(v);
+      const uint16_t lo = to_bf16_rne(v - __uint_as_float((uint32_t)hi << 16));
+      word = (uint32_t)hi | ((uint32_t)lo << 16);
+    }
+    out[mp + e] = word;
   }
 }
 
@@ -141,7 +153,7 @@ __global__ __launch_bounds__(256) void k_spmv_plain(const int32_t* __restrict__ 
 
 __global__ __launch_bounds__(kMmThreads) void k_spmm_tile(PlanView P, const float* __restrict__ X,
                                                          float* __restrict__ Y, int n, int use_mfma) {
-  __shared__ float ys[kMmRows * kMmCols + kMmBlkStage * 6];
+  __shared__ float ys[kMmRows * kMmCols + kMmBlkStage * kBlkDesc];
   const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
   const int t = xcd_tile(blockIdx.x, ntile);
   if (t >= ntile) return;
@@ -242,14 +254,23 @@ void build_schedule(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hip
 }
 
 void build_bf16_split(sable_plan_s& P, hipStream_t s) {
-  if (P.vbr_hi.n != (size_t)P.vbr_cells) {
-    P.vbr_hi.alloc(P.vbr_cells);
-    P.vbr_lo.alloc(P.vbr_cells);
+  if (!P.nblk) return;
+  if (!P.blk_mma_ptr.p) {
+    std::vector<int32_t> blk;
+    to_host(blk, P.blk.p, 4 * (size_t)P.nblk, s);
+    std::vector<i64> mp(P.nblk);
+    i64 acc = 0;
+    for (int b = 0; b < P.nblk; ++b) {
+      mp[b] = acc;
+      const i64 h = blk[4 * b + 1] - blk[4 * b], w = blk[4 * b + 3] - blk[4 * b + 2];
+      acc += h * ((w + 3) & ~(i64)3);
+    }
+    to_dev(P.blk_mma_ptr, mp, s);
+    P.vbr_mma.alloc(acc);
   }
-  if (P.vbr_cells) {
-    k_split<<<grid_for(P.vbr_cells, 256), 256, 0, s>>>(P.vbr_val.p, P.vbr_cells, P.vbr_hi.p, P.vbr_lo.p);
-    LAUNCH_CHECK();
-  }
+  k_split_mma<<<(unsigned)P.nblk, 256, 0, s>>>(P.blk.p, P.blk_val_ptr.p, P.blk_mma_ptr.p,
+                                               P.vbr_val.p, P.vbr_mma.p);
+  LAUNCH_CHECK();
 }
 
 static void launch_stream(const PlanView& v, int rpt, bool nt, const float* x, float* y,
@@ -321,7 +342,7 @@ void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStre
   } else {
     const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
     dim3 grid((unsigned)(((ntile + 7) / 8) * 8), (unsigned)((n + kMmCols - 1) / kMmCols));
-    const int mfma = (mode == 0 && P.vbr_hi.p != nullptr && P.nblk > 0) ? 1 : 0;
+    const int mfma = (mode == 0 && P.vbr_mma.p != nullptr && P.nblk > 0) ? 1 : 0;
     k_spmm_tile<<<grid, kMmThreads, 0, s>>>(v, X, Y, n, mfma);
   }
   LAUNCH_CHECK();

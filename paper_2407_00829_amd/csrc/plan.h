@@ -59,7 +59,10 @@ struct sable_plan_s {
   sable::DBuf<int32_t> blk;
   sable::DBuf<sable::i64> blk_val_ptr;
   sable::DBuf<float> vbr_val;
-  sable::DBuf<uint16_t> vbr_hi, vbr_lo;  // bf16 split copies (same layout as vbr_val)
+  // bf16 split copies for matrix-core SpMM: per block row-major with the row stride padded
+  // to a multiple of 4 (w4), each element one 32-bit word (hi | lo << 16)
+  sable::DBuf<uint32_t> vbr_mma;
+  sable::DBuf<sable::i64> blk_mma_ptr;
   // CSR remainder
   sable::i64 csr_nnz = 0;
   sable::DBuf<int32_t> csr_ptr, csr_col;

@@ -25,6 +25,7 @@ constexpr int kMmRows = 64;
 constexpr int kMmCols = 128;
 constexpr int kMmThreads = 256;
 constexpr int kMmBlkStage = 256;  // block descriptors staged in LDS per pass
+constexpr int kBlkDesc = 8;       // ints per staged descriptor
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
@@ -44,12 +45,16 @@ __device__ __forceinline__ void stage_blocks(const PlanView& P, int q0, int nq, 
   for (int j = threadIdx.x; j < nq; j += blockDim.x) {
     const int b = P.tile_blk[q0 + j];
     const i64 vp = P.blk_val_ptr[b];
-    sb[6 * j] = P.blk[4 * b];
-    sb[6 * j + 1] = P.blk[4 * b + 1];
-    sb[6 * j + 2] = P.blk[4 * b + 2];
-    sb[6 * j + 3] = P.blk[4 * b + 3];
-    sb[6 * j + 4] = (int)(uint32_t)((uint64_t)vp & 0xffffffffu);
-    sb[6 * j + 5] = (int)(uint32_t)((uint64_t)vp >> 32);
+    const i64 mp = P.blk_mma_ptr ? P.blk_mma_ptr[b] : 0;
+    int* d = sb + kBlkDesc * j;
+    d[0] = P.blk[4 * b];
+    d[1] = P.blk[4 * b + 1];
+    d[2] = P.blk[4 * b + 2];
+    d[3] = P.blk[4 * b + 3];
+    d[4] = (int)(uint32_t)((uint64_t)vp & 0xffffffffu);
+    d[5] = (int)(uint32_t)((uint64_t)vp >> 32);
+    d[6] = (int)(uint32_t)((uint64_t)mp & 0xffffffffu);
+    d[7] = (int)(uint32_t)((uint64_t)mp >> 32);
   }
   __syncthreads();
 }
@@ -60,7 +65,7 @@ __device__ __forceinline__ void stage_blocks(const PlanView& P, int q0, int nq, 
 __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int n,
                                           const float* __restrict__ X, float* __restrict__ Y,
                                           float* __restrict__ ys, bool use_mfma) {
-  int* sb = reinterpret_cast<int*>(ys + kMmRows * kMmCols);  // [kMmBlkStage][6]
+  int* sb = reinterpret_cast<int*>(ys + kMmRows * kMmCols);  // [kMmBlkStage][kBlkDesc]
   const int nc = min(kMmCols, n - cb);
   const int rend = min(r0 + kMmRows, P.nrows);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -115,50 +120,53 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
      const int nq = min(kMmBlkStage, bhi - q0);
      stage_blocks(P, q0, nq, sb);
      for (int j = 0; j < nq; ++j) {
-      const int br0 = sb[6 * j], br1 = sb[6 * j + 1];
+      const int* dsc = sb + kBlkDesc * j;
+      const int br0 = dsc[0], br1 = dsc[1];
       const int lo = max(br0, r0), hi = min(br1, rend);
       if (lo >= hi) continue;
-      const int c0 = sb[6 * j + 2], c1 = sb[6 * j + 3];
-      const int h = br1 - br0, w = c1 - c0;
-      const i64 vp = (i64)(((uint64_t)(uint32_t)sb[6 * j + 5] << 32) | (uint32_t)sb[6 * j + 4]);
+      const int c0 = dsc[2], c1 = dsc[3];
+      const int w = c1 - c0, w4 = (w + 3) & ~3;
+      const i64 mp = (i64)(((uint64_t)(uint32_t)dsc[7] << 32) | (uint32_t)dsc[6]);
+      for (int k0 = 0; k0 < w; k0 += 16) {
+        const int kk = k0 + 4 * kg;  // first of this lane's four k values
+        // B fragments (both column chunks) and A fragments (every 16-row slice) first
+        bf16x4_t bh[2], bl[2];
 #pragma unroll
-      for (int ci = 0; ci < 2; ++ci) {
-        const int nch = wave + 4 * ci;
-        if (nch * 16 >= nc) continue;
-        const int col = nch * 16 + m;
-        const bool cok = col < nc;
-        for (int k0 = 0; k0 < w; k0 += 16) {
-          bf16x4_t bh, bl;
+        for (int ci = 0; ci < 2; ++ci) {
+          const int col = (wave + 4 * ci) * 16 + m;
+          const bool cok = col < nc;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int k = k0 + 4 * kg + i;
+            const int k = kk + i;
             const float xv = (cok && k < w) ? X[(i64)(c0 + k) * n + cb + col] : 0.f;
             const uint16_t xh = bf16_rne_dev(xv);
-            bh[i] = (short)xh;
-            bl[i] = (short)bf16_rne_dev(xv - bf16_f32(xh));
+            bh[ci][i] = (short)xh;
+            bl[ci][i] = (short)bf16_rne_dev(xv - bf16_f32(xh));
           }
+        }
+        uint4 aw[4];
 #pragma unroll
-          for (int mt = 0; mt < 4; ++mt) {
-            const int m0 = r0 + 16 * mt;
-            if (m0 >= hi || m0 + 16 <= lo) continue;
-            const int arow = m0 + m;
-            const bool rok = arow >= lo && arow < hi;
-            bf16x4_t ah, al;
+        for (int mt = 0; mt < 4; ++mt) {
+          const int arow = r0 + 16 * mt + m;
+          aw[mt] = make_uint4(0u, 0u, 0u, 0u);
+          if (arow >= lo && arow < hi && kk < w4)
+            aw[mt] = *reinterpret_cast<const uint4*>(P.vbr_mma + mp + (i64)(arow - br0) * w4 + kk);
+        }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int k = k0 + 4 * kg + i;
-              uint16_t h16 = 0, l16 = 0;
-              if (rok && k < w) {
-                const i64 at = vp + (i64)k * h + (arow - br0);
-                h16 = P.vbr_hi[at];
-                l16 = P.vbr_lo[at];
-              }
-              ah[i] = (short)h16;
-              al[i] = (short)l16;
-            }
-            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[mt][ci], 0, 0, 0);
-            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[mt][ci], 0, 0, 0);
-            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[mt][ci], 0, 0, 0);
+        for (int mt = 0; mt < 4; ++mt) {
+          const int m0 = r0 + 16 * mt;
+          if (m0 >= hi || m0 + 16 <= lo) continue;
+          bf16x4_t ah, al;
+          ah[0] = (short)(aw[mt].x & 0xffffu); al[0] = (short)(aw[mt].x >> 16);
+          ah[1] = (short)(aw[mt].y & 0xffffu); al[1] = (short)(aw[mt].y >> 16);
+          ah[2] = (short)(aw[mt].z & 0xffffu); al[2] = (short)(aw[mt].z >> 16);
+          ah[3] = (short)(aw[mt].w & 0xffffu); al[3] = (short)(aw[mt].w >> 16);
+#pragma unroll
+          for (int ci = 0; ci < 2; ++ci) {
+            if ((wave + 4 * ci) * 16 >= nc) continue;
+            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[ci], acc[mt][ci], 0, 0, 0);
+            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[ci], acc[mt][ci], 0, 0, 0);
+            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[ci], acc[mt][ci], 0, 0, 0);
           }
         }
       }
@@ -181,12 +189,13 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
      const int nq = min(kMmBlkStage, bhi - q0);
      stage_blocks(P, q0, nq, sb);
      for (int j = 0; j < nq; ++j) {
-      const int br0 = sb[6 * j], br1 = sb[6 * j + 1];
+      const int* dsc = sb + kBlkDesc * j;
+      const int br0 = dsc[0], br1 = dsc[1];
       const int lo = max(br0, r0), hi = min(br1, rend);
       if (lo >= hi) continue;
-      const int c0 = sb[6 * j + 2], c1 = sb[6 * j + 3];
+      const int c0 = dsc[2], c1 = dsc[3];
       const int h = br1 - br0, w = c1 - c0;
-      const i64 vp = (i64)(((uint64_t)(uint32_t)sb[6 * j + 5] << 32) | (uint32_t)sb[6 * j + 4]);
+      const i64 vp = (i64)(((uint64_t)(uint32_t)dsc[5] << 32) | (uint32_t)dsc[4]);
       for (int rl = wave * rpw + sub; rl < kMmRows; rl += 4 * rpw) {
         const int r = r0 + rl;
         if (r < lo || r >= hi) continue;
