@@ -120,7 +120,9 @@ typedef struct {
   int64_t device_bytes;    /* device memory held by the plan */
   double plan_ms;          /* wall time of sable_plan */
   int32_t spmv_variant, spmm_variant, plain_variant; /* kernel variants in use */
-  int32_t pad1;
+  int32_t far_split;       /* 1 if the streamed SpMV variants gather far-column CSR entries
+                              in a separate pass (see sable_spmv) */
+  int64_t far_nnz;         /* CSR entries handled by that pass */
 } sable_plan_stats;
 
 /* Host buffers for sable_plan_export, sized from sable_plan_info:
@@ -172,7 +174,13 @@ sable_status sable_plan_export(sable_plan_t p, const sable_partition_host* out);
 
 /* y = A x over all regions in one fused launch (Sec. 3.4 shared output): per row
  * (sum over VDIA segments + sum over VBR blocks) + sum over CSR entries, in a fixed order,
- * so results are bitwise reproducible. x[ncols], y[nrows] device fp32. */
+ * so results are bitwise reproducible. x[ncols], y[nrows] device fp32.
+ * Far-column split: for wide matrices (more than 2^20 columns) whose CSR part has at least
+ * 2^16 entries more than 2^17 columns away from their row, the streamed variants first run
+ * a gather pass over those entries (grouped by 16384-column slices of x, each staged in
+ * LDS) into a product buffer owned by the plan, then the fused launch adds the products
+ * in the same order as without the pass. Two calls with the same plan must therefore not
+ * run concurrently on different streams. */
 sable_status sable_spmv(sable_plan_t p, const float* x, float* y, void* stream);
 
 /* Y = A X with n >= 1 right-hand sides (row-major, App. A.2). VBR blocks run on matrix
@@ -206,7 +214,8 @@ sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, const float* 
  *        1/2/4/8/16 lanes per CSR row, 8..10 = 0..2 with non-temporal matrix loads;
  * op 1 = SpMM: 0 tiled with matrix-core blocks, 1 tiled fp32, 2 one wave per row;
  * op 2 = plain CSR baseline: 0..2 streamed, 3..9 with 1..64 lanes per row, 10..12 = 0..2
- *        with non-temporal matrix loads.
+ *        with non-temporal matrix loads;
+ * op 3 = far-column split of the streamed SpMV variants: 0 off, 1 on (when the plan has one).
  * Every variant computes the same product; each is bitwise reproducible on its own. */
 sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32_t variant);
 

@@ -126,6 +126,7 @@ void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list
     build_schedule(P, P.sched_plain[k], 256 << k, false, s);
   }
   build_schedule(P, P.sched_mm, 64, true, s);
+  build_far_split(P, s);
   HIPC(hipStreamSynchronize(s));
   P.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -161,6 +162,8 @@ sable::i64 sable_plan_s::device_bytes() const {
     b += S->tile_seg_lo.bytes() + S->tile_seg_hi.bytes() + S->tile_blk_ptr.bytes() +
          S->tile_blk.bytes();
   }
+  b += far.ccol.bytes() + far.far_col.bytes() + far.far_src.bytes() + far.far_val.bytes() +
+       far.far_prod.bytes() + far.chunk.bytes();
   return b;
 }
 
@@ -270,6 +273,8 @@ sable_status sable_plan_info(sable_plan_t p, sable_plan_stats* o) {
     o->spmv_variant = p->prm.spmv_variant;
     o->spmm_variant = p->prm.spmm_mode;
     o->plain_variant = p->prm.plain_variant;
+    o->far_split = (p->far.npanel && p->prm.far_split) ? 1 : 0;
+    o->far_nnz = p->far.nfar;
   });
 }
 
@@ -340,6 +345,7 @@ sable_status sable_update_values(sable_plan_t p, const float* values, void* stre
       LAUNCH_CHECK();
     }
     if (p->vbr_cells && (p->flags & SABLE_F_SPLIT_BF16)) build_bf16_split(*p, s);
+    refresh_far_values(*p, s);
   });
 }
 

@@ -29,9 +29,19 @@ struct PlanView {
   const int32_t* tile_seg_hi;
   const int32_t* tile_blk_ptr;
   const int32_t* tile_blk;
+  // far-column split: when far_prod is set, csr_col holds negative codes -(1 + q) for entries
+  // whose product far_prod[q] the gather pass has already computed
+  const float* far_prod;
 };
 
-PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain);
+// far = true: the view with the far-column split, if the plan has one and it is enabled.
+PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool far = false);
+
+// CSR term k of the view: a[k] * x[col[k]], or the precomputed far product.
+__device__ __forceinline__ float csr_term(const PlanView& P, int j, float a, const float* __restrict__ x) {
+  if (j >= 0) return a * x[j];
+  return P.far_prod[-j - 1];
+}
 
 // ---- SpMV tile body --------------------------------------------------------------------
 // blockDim.x == rows_per_tile threads; thread t owns row tile*rows_per_tile + t for the band
@@ -99,15 +109,20 @@ __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const flo
 
 // ---- SpMV tile body, streamed variant ---------------------------------------------------
 // Tile = 256*RPT rows, 256 threads; thread t owns rows r0 + t + 256*q (q < RPT).
-//  1. bands: lane per row, diagonals unrolled by 4 (independent value and x loads);
+//  0. every per-tile index load that depends on nothing else is issued at once, then the
+//     first pass of CSR entries (kCsrU per thread: column, value, gathered x), so that the
+//     longest dependent chain of the tile is in flight while the bands run;
+//  1. bands: lane per row, diagonals unrolled by 4 (independent value and x loads); the next
+//     segment's descriptor is loaded while the current one is processed;
 //  2. blocks: each block's rows in the tile x column slices are spread over all threads;
 //     slice partials meet in LDS and are added per row in slice order;
-//  3. CSR: the tile's entries are contiguous, so they are read in coalesced chunks, each
-//     thread multiplies entries by gathered x values into LDS, then every row adds its own
-//     products in index order.
+//  3. CSR: the tile's entries are contiguous and are taken in passes of kCsrChunk; each
+//     thread multiplies kCsrU entries by gathered x values (far entries of a split plan:
+//     their stored products) into LDS, then every row adds its own products in index order.
 // Per row: y = (bands + blocks) + CSR, in a fixed order (bitwise reproducible).
 constexpr int kSpmvThreads = 256;
-constexpr int kCsrChunk = 4096;
+constexpr int kCsrU = 8;                          // CSR entries per thread per pass
+constexpr int kCsrChunk = kCsrU * kSpmvThreads;  // entries per pass
 
 __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
   // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of tiles so
@@ -124,6 +139,25 @@ __device__ __forceinline__ T ld(const T* p) {
   else return *p;
 }
 
+// One CSR pass: thread t takes entries e0 + t + 256*u (u < kCsrU) below e_end.
+template <bool NT>
+__device__ __forceinline__ void csr_pass(const PlanView& P, int e0, int e_end,
+                                         const float* __restrict__ x, float (&pv)[kCsrU]) {
+  int jj[kCsrU];
+  float aa[kCsrU];
+#pragma unroll
+  for (int u = 0; u < kCsrU; ++u) {
+    const int k = e0 + (int)threadIdx.x + kSpmvThreads * u;
+    jj[u] = k < e_end ? ld<NT>(P.csr_col + k) : 0;
+    aa[u] = k < e_end ? ld<NT>(P.csr_val + k) : 0.f;
+  }
+#pragma unroll
+  for (int u = 0; u < kCsrU; ++u) {
+    const int k = e0 + (int)threadIdx.x + kSpmvThreads * u;
+    pv[u] = k < e_end ? csr_term(P, jj[u], aa[u], x) : 0.f;
+  }
+}
+
 template <int RPT, bool NT = false>
 __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
                                                  const float* __restrict__ x,
@@ -134,42 +168,72 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
   const int r0 = tile * RT;
   const int t = threadIdx.x;
   const int rend = min(r0 + RT, P.nrows);
+  // 0. independent loads, then the first CSR pass
+  const int e_begin = P.csr_ptr[r0], e_end = P.csr_ptr[rend];
+  const int slo = P.tile_seg_lo[tile], shi = P.tile_seg_hi[tile];
+  const int blo = P.tile_blk_ptr[tile], bhi = P.tile_blk_ptr[tile + 1];
+  int kb[RPT], ke[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = r0 + t + kSpmvThreads * q;
+    kb[q] = r < rend ? P.csr_ptr[r] : 0;
+    ke[q] = r < rend ? P.csr_ptr[r + 1] : 0;
+  }
+  int rs = 0, nr = 0, nd = 0;
+  i64 svp = 0;
+  int sip = 0;
+  if (slo < shi) {
+    rs = P.seg_row_start[slo];
+    nr = P.seg_nrows[slo];
+    nd = P.seg_ndiags[slo];
+    svp = P.seg_val_ptr[slo];
+    sip = P.seg_idiag_ptr[slo];
+  }
+  float pv[kCsrU];
+  csr_pass<NT>(P, e_begin, e_end, x, pv);
+
   float acc[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) acc[q] = 0.f;
   // 1. band segments
-  const int slo = P.tile_seg_lo[tile], shi = P.tile_seg_hi[tile];
   for (int s = slo; s < shi; ++s) {
-    const int rs = P.seg_row_start[s], nr = P.seg_nrows[s], nd = P.seg_ndiags[s];
-    const int32_t* od = P.idiag + P.seg_idiag_ptr[s];
-    const float* vb = P.vdia_val + P.seg_val_ptr[s];
+    const int32_t* od = P.idiag + sip;
+    const float* vb = P.vdia_val + svp;
+    const int crs = rs, cnr = nr, cnd = nd;
+    if (s + 1 < shi) {  // next descriptor
+      rs = P.seg_row_start[s + 1];
+      nr = P.seg_nrows[s + 1];
+      nd = P.seg_ndiags[s + 1];
+      svp = P.seg_val_ptr[s + 1];
+      sip = P.seg_idiag_ptr[s + 1];
+    }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int r = r0 + t + kSpmvThreads * q;
-      if (r < rs || r >= rs + nr || r >= rend) continue;
-      const float* v = vb + (r - rs);
-      int d = 0;
-      for (; d + 4 <= nd; d += 4) {
-        const int c0 = r + od[d], c1 = r + od[d + 1], c2 = r + od[d + 2], c3 = r + od[d + 3];
-        const float v0 = ld<NT>(v + (i64)d * nr), v1 = ld<NT>(v + (i64)(d + 1) * nr),
-                    v2 = ld<NT>(v + (i64)(d + 2) * nr), v3 = ld<NT>(v + (i64)(d + 3) * nr);
-        const float x0 = (unsigned)c0 < (unsigned)P.ncols ? x[c0] : 0.f;
-        const float x1 = (unsigned)c1 < (unsigned)P.ncols ? x[c1] : 0.f;
-        const float x2 = (unsigned)c2 < (unsigned)P.ncols ? x[c2] : 0.f;
-        const float x3 = (unsigned)c3 < (unsigned)P.ncols ? x[c3] : 0.f;
-        acc[q] += v0 * x0;
-        acc[q] += v1 * x1;
-        acc[q] += v2 * x2;
-        acc[q] += v3 * x3;
-      }
-      for (; d < nd; ++d) {
-        const int c = r + od[d];
-        if ((unsigned)c < (unsigned)P.ncols) acc[q] += ld<NT>(v + (i64)d * nr) * x[c];
+      if (r < crs || r >= crs + cnr || r >= rend) continue;
+      const float* v = vb + (r - crs);
+      // groups of four diagonals with predicated loads (a ribbon of 3 is one group)
+      for (int d = 0; d < cnd; d += 4) {
+        int c[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          c[u] = d + u < cnd ? r + od[d + u] : -1;
+          ok[u] = (unsigned)c[u] < (unsigned)P.ncols;
+        }
+        float vv[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          vv[u] = ok[u] ? ld<NT>(v + (i64)(d + u) * cnr) : 0.f;
+          xv[u] = ok[u] ? x[c[u]] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (ok[u]) acc[q] += vv[u] * xv[u];
       }
     }
   }
   // 2. blocks
-  const int blo = P.tile_blk_ptr[tile], bhi = P.tile_blk_ptr[tile + 1];
   for (int qb = blo; qb < bhi; ++qb) {
     const int b = P.tile_blk[qb];
     const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
@@ -221,33 +285,16 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
       acc[q] += sacc;
     }
   }
-  // 3. CSR entries of the tile, streamed through LDS
+  // 3. CSR: the first pass is already in registers
   float cs[RPT];
-  int kb[RPT], ke[RPT];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = r0 + t + kSpmvThreads * q;
-    cs[q] = 0.f;
-    kb[q] = r < rend ? P.csr_ptr[r] : 0;
-    ke[q] = r < rend ? P.csr_ptr[r + 1] : 0;
-  }
-  const int e_begin = P.csr_ptr[r0], e_end = P.csr_ptr[rend];
+  for (int q = 0; q < RPT; ++q) cs[q] = 0.f;
   for (int e0 = e_begin; e0 < e_end; e0 += kCsrChunk) {
+    if (e0 != e_begin) csr_pass<NT>(P, e0, e_end, x, pv);
     const int n = min(kCsrChunk, e_end - e0);
-    __syncthreads();
-    int i = t;
-    for (; i + 3 * kSpmvThreads < n; i += 4 * kSpmvThreads) {
-      const int k0 = e0 + i, k1 = k0 + kSpmvThreads, k2 = k1 + kSpmvThreads, k3 = k2 + kSpmvThreads;
-      const int j0 = ld<NT>(P.csr_col + k0), j1 = ld<NT>(P.csr_col + k1),
-                j2 = ld<NT>(P.csr_col + k2), j3 = ld<NT>(P.csr_col + k3);
-      const float a0 = ld<NT>(P.csr_val + k0), a1 = ld<NT>(P.csr_val + k1),
-                  a2 = ld<NT>(P.csr_val + k2), a3 = ld<NT>(P.csr_val + k3);
-      prod[i] = a0 * x[j0];
-      prod[i + kSpmvThreads] = a1 * x[j1];
-      prod[i + 2 * kSpmvThreads] = a2 * x[j2];
-      prod[i + 3 * kSpmvThreads] = a3 * x[j3];
-    }
-    for (; i < n; i += kSpmvThreads) prod[i] = ld<NT>(P.csr_val + e0 + i) * x[ld<NT>(P.csr_col + e0 + i)];
+    __syncthreads();  // previous pass's row sums are done with prod
+#pragma unroll
+    for (int u = 0; u < kCsrU; ++u) prod[t + kSpmvThreads * u] = pv[u];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {

@@ -6,7 +6,7 @@
 
 namespace sable {
 
-PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain) {
+PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool far) {
   PlanView v;
   std::memset(&v, 0, sizeof(v));
   v.nrows = P.nrows;
@@ -40,6 +40,10 @@ PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain) {
   v.csr_ptr = P.csr_ptr.p;
   v.csr_col = P.csr_col.p;
   v.csr_val = P.csr_val.p;
+  if (far && P.far.npanel && P.prm.far_split) {
+    v.csr_col = P.far.ccol.p;
+    v.far_prod = P.far.far_prod.p;
+  }
   return v;
 }
 
@@ -140,6 +144,63 @@ __global__ __launch_bounds__(256) void k_spmv_stream(PlanView P, const float* __
   const int tile = xcd_tile(blockIdx.x, P.ntiles);
   if (tile >= P.ntiles) return;
   spmv_tile_stream<RPT, NT>(P, tile, x, y, lds);
+}
+
+// Far-column gather: workgroup b runs on XCD b mod 8 and takes that XCD's (b / 8)-th work
+// item (begin, end, panel); it stages the panel's x slice in LDS with coalesced loads, then
+// multiplies its entries by x values read from LDS.
+__global__ __launch_bounds__(kFarThreads) void k_far_gather(const int32_t* __restrict__ chunk,
+                                                           int per_xcd, int ncols,
+                                                           const int32_t* __restrict__ col,
+                                                           const float* __restrict__ val,
+                                                           const float* __restrict__ x,
+                                                           float* __restrict__ prod) {
+  __shared__ float xs[kFarPanelCols];
+  const int* c = chunk + 3 * ((blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3));
+  const int b = c[0], e = c[1], panel = c[2];
+  if (b < 0) return;
+  const int t = threadIdx.x;
+  const int base = panel * kFarPanelCols;
+  const int w = min(kFarPanelCols, ncols - base);
+  // this thread's entries first (independent of the slice), then the slice
+  int j[8];
+  float a[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int k = b + t + kFarThreads * u;
+    j[u] = k < e ? __builtin_nontemporal_load(col + k) - base : 0;
+    a[u] = k < e ? __builtin_nontemporal_load(val + k) : 0.f;
+  }
+  // slice: all loads of a thread in flight together (float4 when x is 16-byte aligned)
+  constexpr int kV = kFarPanelCols / (4 * kFarThreads);  // float4 per thread
+  if (((uintptr_t)x & 15) == 0 && w == kFarPanelCols) {
+    float4 v[kV];
+    const float4* x4 = reinterpret_cast<const float4*>(x + base);
+#pragma unroll
+    for (int u = 0; u < kV; ++u) v[u] = x4[t + kFarThreads * u];
+#pragma unroll
+    for (int u = 0; u < kV; ++u) reinterpret_cast<float4*>(xs)[t + kFarThreads * u] = v[u];
+  } else {
+    for (int i0 = 0; i0 < w; i0 += 8 * kFarThreads) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + t + kFarThreads * u;
+        v[u] = i < w ? x[base + i] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + t + kFarThreads * u;
+        if (i < w) xs[i] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int k = b + t + kFarThreads * u;
+    if (k < e) prod[k] = a[u] * xs[j[u]];
+  }
 }
 
 template <int W>
@@ -296,7 +357,14 @@ void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s)
   const int var = P.prm.spmv_variant;
   if (var <= 2 || var >= 8) {
     const int k = var <= 2 ? var : var - 8;
-    launch_stream(make_view(P, P.sched[k], false), 1 << k, var >= 8, x, y, s);
+    const PlanView v = make_view(P, P.sched[k], false, true);
+    if (v.far_prod) {
+      k_far_gather<<<(unsigned)(8 * P.far.per_xcd), kFarThreads, 0, s>>>(
+          P.far.chunk.p, P.far.per_xcd, P.ncols, P.far.far_col.p, P.far.far_val.p, x,
+          P.far.far_prod.p);
+      LAUNCH_CHECK();
+    }
+    launch_stream(v, 1 << k, var >= 8, x, y, s);
     return;
   }
   const PlanView v = make_view(P, P.sched[0], false);

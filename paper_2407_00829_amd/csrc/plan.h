@@ -32,6 +32,35 @@ struct ExecParams {
   int spmv_variant = 1;
   int plain_variant = 1;
   int spmm_mode = 0;  // fused SpMM variant
+  int far_split = 1;  // streamed SpMV: gather far-column CSR entries in a separate pass
+};
+
+// Far-column split of the CSR remainder (streamed SpMV variants). An entry whose column lies
+// more than kFarWindow columns from its row would pull a whole cache line of x for one
+// 4-byte value, and a wave of such entries issues 64 separate cache requests. Such entries
+// are grouped by column panel (x slices of kFarPanelCols columns); a gather pass stages a
+// panel's x slice in LDS with coalesced loads and multiplies the panel's entries by it,
+// writing the products in panel order (panel p's workgroups run on XCD p mod 8, so repeated
+// slice loads hit one L2). The tile kernel walks the CSR part as usual over ccol, a copy of
+// csr_col in which a far entry's column is replaced by -(1 + position of its product), and
+// takes the stored product for it. The order of every row's sum is unchanged, so results
+// equal those without the split bit for bit.
+constexpr int kFarWindow = 1 << 17;      // |column - row| above this is far
+constexpr int kFarPanelCols = 1 << 14;   // x slice per panel: 64 KB of fp32 in LDS
+constexpr int kFarThreads = 512;
+constexpr int kFarChunk = 8 * kFarThreads;  // entries per gather workgroup
+constexpr int kFarMinEntries = 1 << 16;  // below this the extra pass is not worth a launch
+constexpr int kFarMinCols = 1 << 20;     // x below 4 MB stays L2-resident anyway
+
+struct FarSplit {
+  int npanel = 0;  // 0: no split
+  int panel_cols = 0;
+  int per_xcd = 0;  // gather workgroups per XCD
+  i64 nfar = 0;
+  DBuf<int32_t> ccol;                 // csr_col with far entries encoded as -(1 + q)
+  DBuf<int32_t> far_col, far_src;     // panel-major (row order within a panel); src = CSR index
+  DBuf<float> far_val, far_prod;
+  DBuf<int32_t> chunk;  // [8][per_xcd] (begin, end) entry ranges, begin < 0 = none
 };
 
 struct Schedule {
@@ -76,6 +105,7 @@ struct sable_plan_s {
   sable::Schedule sched[3];        // tiles of 256, 512, 1024 rows with the formats
   sable::Schedule sched_plain[3];  // the same tilings for the whole input as CSR
   sable::Schedule sched_mm;        // 64-row tiles of the fused SpMM
+  sable::FarSplit far;             // far-column split of the CSR part (streamed SpMV)
   sable::ExecParams prm;
   uint32_t flags = 0;
   double plan_ms = 0.0;
@@ -101,6 +131,8 @@ bool validate_csr_device(const sable_csr& A, hipStream_t s);
 void build_schedule(sable_plan_s& P, Schedule& S, int rows_per_tile, bool with_formats,
                     hipStream_t s);
 void build_bf16_split(sable_plan_s& P, hipStream_t s);
+void build_far_split(sable_plan_s& P, hipStream_t s);
+void refresh_far_values(sable_plan_s& P, hipStream_t s);
 void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s);

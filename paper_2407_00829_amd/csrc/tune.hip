@@ -39,6 +39,13 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
       if (t < best) { best = t; bv = v; }
     }
     P.prm.spmv_variant = bv;
+    if (P.far.npanel && (bv <= 2 || bv >= 8)) {
+      P.prm.far_split = 0;
+      const float t0 = time_ms([&] { launch_spmv(P, x, y, s); }, s, reps);
+      P.prm.far_split = 1;
+      const float t1 = time_ms([&] { launch_spmv(P, x, y, s); }, s, reps);
+      P.prm.far_split = t1 <= t0 ? 1 : 0;
+    }
     best = 1e30f;
     bv = 0;
     for (int v = 0; v <= 12; ++v) {
@@ -87,13 +94,14 @@ extern "C" sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32
     sable::set_error("NULL plan");
     return SABLE_ERR_INVALID_ARG;
   }
-  const int maxv = op == 0 ? 10 : op == 1 ? 2 : op == 2 ? 12 : -1;
+  const int maxv = op == 0 ? 10 : op == 1 ? 2 : op == 2 ? 12 : op == 3 ? 1 : -1;
   if (variant < 0 || variant > maxv) {
     sable::set_error("variant %d out of range for op %d", variant, op);
     return SABLE_ERR_INVALID_ARG;
   }
   if (op == 0) p->prm.spmv_variant = variant;
   else if (op == 1) p->prm.spmm_mode = variant;
-  else p->prm.plain_variant = variant;
+  else if (op == 2) p->prm.plain_variant = variant;
+  else p->prm.far_split = variant;
   return SABLE_OK;
 }

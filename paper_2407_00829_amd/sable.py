@@ -68,7 +68,8 @@ class sable_plan_stats(ctypes.Structure):
                 ("csr_nnz", ctypes.c_int64), ("bytes_matrix", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("plan_ms", ctypes.c_double),
                 ("spmv_variant", ctypes.c_int32), ("spmm_variant", ctypes.c_int32),
-                ("plain_variant", ctypes.c_int32), ("pad1", ctypes.c_int32)]
+                ("plain_variant", ctypes.c_int32), ("far_split", ctypes.c_int32),
+                ("far_nnz", ctypes.c_int64)]
 
 
 class sable_partition_host(ctypes.Structure):
@@ -220,7 +221,7 @@ def sable_plan(nrows, ncols, indptr, indices, values, kinds, vbr_mode=SABLE_VBR_
 def sable_plan_info(p: Plan) -> dict:
     s = sable_plan_stats()
     _check("sable_plan_info", lib().sable_plan_info(p.h, ctypes.byref(s)))
-    return {k: getattr(s, k) for k, _ in s._fields_ if k not in ("pad0", "pad1")}
+    return {k: getattr(s, k) for k, _ in s._fields_ if k != "pad0"}
 
 
 def sable_plan_export(p: Plan) -> dict:

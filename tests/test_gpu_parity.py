@@ -282,3 +282,66 @@ def test_c2_full_size_sampled(seed):
     err = oracle.rel_err(y.cpu().numpy()[rows], oracle.spmv_rows(A, x, rows))
     print(f"  sampled rel_err={err:.3e}")
     assert err <= 1e-5
+
+
+# ---- far-column split of the CSR part (streamed SpMV) ------------------------------------
+
+FAR_WINDOW = 1 << 17  # entries more than this many columns from their row are far
+
+
+def wide_scatter(nr, nc, seed):
+    """Main diagonal (a VDIA band) plus ~0.15 uniform-random entries per row and 70,000
+    more, so that the CSR part has well over 2^16 far entries and rows of uneven length."""
+    rng = np.random.default_rng(seed)
+    d = np.arange(min(nr, nc))
+    ns = int(0.15 * nr) + 70000
+    rows = np.concatenate([d, rng.integers(0, nr, ns)])
+    cols = np.concatenate([d, rng.integers(0, nc, ns)])
+    vals = rng.uniform(-1, 1, rows.size).astype(np.float32)
+    return synth.from_coo(nr, nc, rows, cols, vals)
+
+
+@pytest.mark.parametrize("shape", [(1_300_001, 1_300_001), (200_003, 3_000_000),
+                                   (2_000_000, 1_100_000)])
+def test_far_column_split(shape):
+    """Square, wide and tall matrices: the plan reports the far-entry count the CSR export
+    implies; every streamed variant matches the oracle with the split on and off, and the
+    two agree bit for bit (the split keeps each row's summation order); a value refresh
+    reaches the gathered copies."""
+    nr, nc = shape
+    A = wide_scatter(nr, nc, seed=nr % 97)
+    x = synth.gen_dense_vector(1, nc)
+    p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, oracle.Thresholds())
+    info = sable.sable_plan_info(p)
+    got = sable.sable_plan_export(p)
+    ptr = np.asarray(got["csr_ptr"], np.int64)
+    erow = np.repeat(np.arange(nr, dtype=np.int64), np.diff(ptr))
+    nfar = int(np.count_nonzero(np.abs(got["csr_col"].astype(np.int64) - erow) > FAR_WINDOW))
+    print(f"  far entries {nfar} of {got['csr_col'].size}", flush=True)
+    assert nfar >= 1 << 16
+    assert info["far_split"] == 1 and info["far_nnz"] == nfar
+    for v in (0, 1, 2, 8, 9, 10):
+        sable.sable_plan_set_variant(p, 0, v)
+        ys = []
+        for fs in (1, 0):
+            sable.sable_plan_set_variant(p, 3, fs)
+            print(f"  variant {v} far_split {fs}", flush=True)
+            check_spmv(p, A, x)
+            ys.append(run_spmv(p, A, x))
+        assert torch.equal(ys[0].view(torch.int32), ys[1].view(torch.int32)), v
+    sable.sable_plan_set_variant(p, 0, 1)
+    sable.sable_plan_set_variant(p, 3, 1)
+    A2 = synth.CSR(A.nrows, A.ncols, A.indptr, A.indices,
+                   synth.gen_dense_vector(5, A.nnz, normal=True))
+    sable.sable_update_values(p, torch.from_numpy(A2.values).cuda())
+    torch.cuda.synchronize()
+    check_spmv(p, A2, x)
+
+
+def test_far_split_absent_below_thresholds():
+    """Narrow matrices (x within a few MB) and CSR parts with few far entries keep the
+    single fused launch."""
+    A = wide_scatter(500_000, 500_000, seed=3)
+    p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, oracle.Thresholds())
+    assert sable.sable_plan_info(p)["far_split"] == 0
+    check_spmv(p, A, synth.gen_dense_vector(2, A.ncols))
