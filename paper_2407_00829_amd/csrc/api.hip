@@ -160,7 +160,7 @@ sable::i64 sable_plan_s::device_bytes() const {
   for (int k = 0; k < 7; ++k) {
     const sable::Schedule* S = k < 3 ? &sched[k] : k < 6 ? &sched_plain[k - 3] : &sched_mm;
     b += S->tile_seg_lo.bytes() + S->tile_seg_hi.bytes() + S->tile_blk_ptr.bytes() +
-         S->tile_blk.bytes();
+         S->tile_blk.bytes() + S->order.bytes();
   }
   b += far.ccol.bytes() + far.far_col.bytes() + far.far_src.bytes() + far.far_val.bytes() +
        far.far_prod.bytes() + far.chunk.bytes();

@@ -56,13 +56,16 @@ __global__ __launch_bounds__(256) void k_batch(const PlanView* __restrict__ view
     const int it = lo;
     const BatchItemDev I = items[it];
     const PlanView& P = views[it];
-    const int local = (int)(u - unit_off[it]);
+    int local = (int)(u - unit_off[it]);
     if (I.op == 0) {
+      if (P.tile_order) local = P.tile_order[local];
       if (I.rpt == 1) spmv_tile_stream<1>(P, local, I.x, I.y, lds);
       else if (I.rpt == 2) spmv_tile_stream<2>(P, local, I.x, I.y, lds);
       else spmv_tile_stream<4>(P, local, I.x, I.y, lds);
     } else {
-      const int rt = local % I.units_per_col, cc = local / I.units_per_col;
+      int rt = local % I.units_per_col;
+      const int cc = local / I.units_per_col;
+      if (P.tile_order) rt = P.tile_order[rt];
       spmm_tile(P, rt * kMmRows, cc * kMmCols, I.n, I.x, I.y, lds, I.mfma != 0);
     }
     __syncthreads();

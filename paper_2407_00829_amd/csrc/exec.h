@@ -29,6 +29,7 @@ struct PlanView {
   const int32_t* tile_seg_hi;
   const int32_t* tile_blk_ptr;
   const int32_t* tile_blk;
+  const int32_t* tile_order;  // launch order of the streamed kernels (may be null)
   // far-column split: when far_prod is set, csr_col holds negative codes -(1 + q) for entries
   // whose product far_prod[q] the gather pass has already computed
   const float* far_prod;
@@ -110,21 +111,25 @@ __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const flo
 // ---- SpMV tile body, streamed variant ---------------------------------------------------
 // Tile = 256*RPT rows, 256 threads; thread t owns rows r0 + t + 256*q (q < RPT).
 //  0. every per-tile index load that depends on nothing else is issued at once, then the
-//     first pass of CSR entries (kCsrU per thread: column, value, gathered x), so that the
+//     first pass of CSR entries (U per thread: column, value, gathered x), so that the
 //     longest dependent chain of the tile is in flight while the bands run;
 //  1. bands: lane per row, diagonals unrolled by 4 (independent value and x loads); the next
 //     segment's descriptor is loaded while the current one is processed;
 //  2. blocks: each block's rows in the tile x column slices are spread over all threads;
 //     slice partials meet in LDS and are added per row in slice order;
-//  3. CSR: the tile's entries are contiguous and are taken in passes of kCsrChunk; each
-//     thread multiplies kCsrU entries by gathered x values (far entries of a split plan:
+//  3. CSR: the tile's entries are contiguous and are taken in passes of 256*U; each
+//     thread multiplies U entries by gathered x values (far entries of a split plan:
 //     their stored products) into LDS, then every row adds its own products in index order.
 // Per row: y = (bands + blocks) + CSR, in a fixed order (bitwise reproducible).
 constexpr int kSpmvThreads = 256;
-constexpr int kCsrU = 8;                          // CSR entries per thread per pass
-constexpr int kCsrChunk = kCsrU * kSpmvThreads;  // entries per pass
+constexpr int kCsrUMax = 16;                        // CSR entries per thread per pass (max)
+constexpr int kCsrChunk = kCsrUMax * kSpmvThreads;  // LDS products per pass (max)
+template <int RPT>
+struct CsrPass {
+  static constexpr int U = RPT == 1 ? 8 : kCsrUMax;  // entries per thread per pass
+};
 
-__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+__host__ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
   // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of tiles so
   // neighbouring rows (and their x entries) share one L2
   const int per = (ntiles + 7) >> 3;
@@ -139,20 +144,20 @@ __device__ __forceinline__ T ld(const T* p) {
   else return *p;
 }
 
-// One CSR pass: thread t takes entries e0 + t + 256*u (u < kCsrU) below e_end.
-template <bool NT>
+// One CSR pass: thread t takes entries e0 + t + 256*u (u < U) below e_end.
+template <bool NT, int U>
 __device__ __forceinline__ void csr_pass(const PlanView& P, int e0, int e_end,
-                                         const float* __restrict__ x, float (&pv)[kCsrU]) {
-  int jj[kCsrU];
-  float aa[kCsrU];
+                                         const float* __restrict__ x, float (&pv)[U]) {
+  int jj[U];
+  float aa[U];
 #pragma unroll
-  for (int u = 0; u < kCsrU; ++u) {
+  for (int u = 0; u < U; ++u) {
     const int k = e0 + (int)threadIdx.x + kSpmvThreads * u;
     jj[u] = k < e_end ? ld<NT>(P.csr_col + k) : 0;
     aa[u] = k < e_end ? ld<NT>(P.csr_val + k) : 0.f;
   }
 #pragma unroll
-  for (int u = 0; u < kCsrU; ++u) {
+  for (int u = 0; u < U; ++u) {
     const int k = e0 + (int)threadIdx.x + kSpmvThreads * u;
     pv[u] = k < e_end ? csr_term(P, jj[u], aa[u], x) : 0.f;
   }
@@ -163,7 +168,9 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
                                                  const float* __restrict__ x,
                                                  float* __restrict__ y, float* __restrict__ lds) {
   constexpr int RT = kSpmvThreads * RPT;
-  float* prod = lds;                 // kCsrChunk products
+  constexpr int U = CsrPass<RPT>::U;
+  constexpr int kPass = U * kSpmvThreads;
+  float* prod = lds;                 // kPass products
   float* part = lds + kCsrChunk;     // RT block partials
   const int r0 = tile * RT;
   const int t = threadIdx.x;
@@ -189,8 +196,8 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
     svp = P.seg_val_ptr[slo];
     sip = P.seg_idiag_ptr[slo];
   }
-  float pv[kCsrU];
-  csr_pass<NT>(P, e_begin, e_end, x, pv);
+  float pv[U];
+  csr_pass<NT, U>(P, e_begin, e_end, x, pv);
 
   float acc[RPT];
 #pragma unroll
@@ -289,12 +296,12 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
   float cs[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) cs[q] = 0.f;
-  for (int e0 = e_begin; e0 < e_end; e0 += kCsrChunk) {
-    if (e0 != e_begin) csr_pass<NT>(P, e0, e_end, x, pv);
-    const int n = min(kCsrChunk, e_end - e0);
+  for (int e0 = e_begin; e0 < e_end; e0 += kPass) {
+    if (e0 != e_begin) csr_pass<NT, U>(P, e0, e_end, x, pv);
+    const int n = min(kPass, e_end - e0);
     __syncthreads();  // previous pass's row sums are done with prod
 #pragma unroll
-    for (int u = 0; u < kCsrU; ++u) prod[t + kSpmvThreads * u] = pv[u];
+    for (int u = 0; u < U; ++u) prod[t + kSpmvThreads * u] = pv[u];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {

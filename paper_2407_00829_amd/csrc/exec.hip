@@ -6,6 +6,8 @@
 
 namespace sable {
 
+void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStream_t s);
+
 PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool far) {
   PlanView v;
   std::memset(&v, 0, sizeof(v));
@@ -17,6 +19,7 @@ PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool fa
   v.tile_seg_hi = S.tile_seg_hi.p;
   v.tile_blk_ptr = S.tile_blk_ptr.p;
   v.tile_blk = S.tile_blk.p;
+  v.tile_order = S.order.p;
   if (plain) {
     v.csr_ptr = P.a_ptr.p;
     v.csr_col = P.a_col.p;
@@ -93,6 +96,28 @@ __global__ void k_tile_ptr(const uint64_t* __restrict__ keys, i64 n, int ntiles,
   }
 }
 
+// Estimated cost of each tile: CSR entries (weight 2: index, value and a gathered x) plus
+// VBR cells plus VDIA cells of the tile.
+__global__ void k_tile_cost(const int32_t* __restrict__ ptr, int nrows, int RT, int ntiles,
+                            const int32_t* __restrict__ slo, const int32_t* __restrict__ shi,
+                            const int32_t* __restrict__ srs, const int32_t* __restrict__ snr,
+                            const int32_t* __restrict__ snd, const int32_t* __restrict__ bptr,
+                            const int32_t* __restrict__ tblk, const int32_t* __restrict__ blk,
+                            i64* __restrict__ cost) {
+  for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < ntiles; t += (i64)gridDim.x * blockDim.x) {
+    const int a = (int)(t * RT), b = (int)min((i64)nrows, (t + 1) * RT);
+    i64 c = 2 * (i64)(ptr[b] - ptr[a]);
+    if (slo)
+      for (int s = slo[t]; s < shi[t]; ++s)
+        c += (i64)(min(b, srs[s] + snr[s]) - max(a, srs[s])) * snd[s];
+    for (int q = bptr[t]; q < bptr[t + 1]; ++q) {
+      const int* B = blk + 4 * tblk[q];
+      c += (i64)(min(b, B[1]) - max(a, B[0])) * (B[3] - B[2]);
+    }
+    cost[t] = c;
+  }
+}
+
 __global__ void k_zero_i32(int32_t* __restrict__ a, i64 n) {
   for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x) a[k] = 0;
 }
@@ -141,8 +166,9 @@ template <int RPT, bool NT>
 __global__ __launch_bounds__(256) void k_spmv_stream(PlanView P, const float* __restrict__ x,
                                                     float* __restrict__ y) {
   __shared__ float lds[kCsrChunk + kSpmvThreads * RPT];
-  const int tile = xcd_tile(blockIdx.x, P.ntiles);
+  int tile = xcd_tile(blockIdx.x, P.ntiles);
   if (tile >= P.ntiles) return;
+  if (P.tile_order) tile = P.tile_order[tile];
   spmv_tile_stream<RPT, NT>(P, tile, x, y, lds);
 }
 
@@ -216,8 +242,9 @@ __global__ __launch_bounds__(kMmThreads) void k_spmm_tile(PlanView P, const floa
                                                          float* __restrict__ Y, int n, int use_mfma) {
   __shared__ float ys[kMmRows * kMmCols + kMmBlkStage * kBlkDesc];
   const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
-  const int t = xcd_tile(blockIdx.x, ntile);
+  int t = xcd_tile(blockIdx.x, ntile);
   if (t >= ntile) return;
+  if (P.tile_order) t = P.tile_order[t];
   spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, use_mfma != 0);
 }
 
@@ -269,7 +296,40 @@ __global__ __launch_bounds__(256) void k_spmm_fused_valu(PlanView P, const float
 
 }  // namespace
 
+static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s);
+
 void build_schedule(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStream_t s) {
+  build_tiles(P, S, RT, with_formats, s);
+  build_order(P, S, with_formats, s);
+}
+
+static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s) {
+  const int nt = S.ntiles;
+  if (nt < 2) return;
+  DBuf<i64> cost(nt);
+  const bool fm = with_formats && P.nseg;
+  k_tile_cost<<<grid_for(nt, 256), 256, 0, s>>>(
+      with_formats ? P.csr_ptr.p : P.a_ptr.p, P.nrows, S.rows_per_tile, nt,
+      fm ? S.tile_seg_lo.p : nullptr, fm ? S.tile_seg_hi.p : nullptr, P.seg_row_start.p,
+      P.seg_nrows.p, P.seg_ndiags.p, S.tile_blk_ptr.p, S.tile_blk.p,
+      with_formats ? P.blk.p : nullptr, cost.p);
+  LAUNCH_CHECK();
+  std::vector<i64> hc;
+  to_host(hc, cost.p, nt, s);
+  // slot i of XCD run x holds tile xcd_tile(8*i + x); sort each run's tiles by cost
+  const int per = (nt + 7) >> 3;
+  std::vector<int32_t> ord(nt);
+  for (int t = 0; t < nt; ++t) ord[t] = t;
+  for (int x = 0; x < 8; ++x) {
+    const int a = std::min(nt, x * per), b = std::min(nt, (x + 1) * per);
+    std::stable_sort(ord.begin() + a, ord.begin() + b,
+                     [&](int32_t u, int32_t v) { return hc[u] > hc[v]; });
+  }
+  to_dev(S.order, ord, s);
+  HIPC(hipStreamSynchronize(s));
+}
+
+void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStream_t s) {
   S.rows_per_tile = RT;
   S.ntiles = (P.nrows + RT - 1) / RT;
   const int nt = S.ntiles;

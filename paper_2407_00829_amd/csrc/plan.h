@@ -68,6 +68,10 @@ struct Schedule {
   int ntiles = 0;
   DBuf<int32_t> tile_seg_lo, tile_seg_hi;  // VDIA segments overlapping each tile
   DBuf<int32_t> tile_blk_ptr, tile_blk;    // VBR blocks overlapping each tile
+  // Launch order of the streamed kernels: workgroup slot i runs tile order[i]. Within each
+  // XCD's contiguous run of slots the tiles are sorted by estimated cost, heaviest first, so
+  // the few expensive tiles (dense blocks, long rows) do not finish last.
+  DBuf<int32_t> order;
 };
 
 }  // namespace sable
