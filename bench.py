@@ -100,12 +100,25 @@ def cpu_baseline_spmm(A, X, rows=20000, target_s=10.0):
             "sample": f"FP64 SpMM (n={n}) of the first {sel.size} rows, {passes} passes ({dt:.1f} s)"}
 
 
-def variant_kernel(v: int) -> str:
+def variant_kernel(v: int, far: int = 0) -> str:
+    """Kernel(s) one hybrid SpMV launches for variant v ('A + B' when the far-column gather
+    pass runs first)."""
     if v <= 2:
-        return f"k_spmv_stream<{1 << v}, false>"
-    if v >= 8:
-        return f"k_spmv_stream<{1 << (v - 8)}, true>"
-    return f"k_spmv_fused<{1 << (v - 3)}>"
+        k = f"k_spmv_stream<{1 << v}, false>"
+    elif v >= 8:
+        k = f"k_spmv_stream<{1 << (v - 8)}, true>"
+    else:
+        return f"k_spmv_fused<{1 << (v - 3)}>"
+    return f"k_far_gather + {k}" if far else k
+
+
+def plain_kernel(v: int) -> str:
+    """Kernel the plain CSR baseline launches for its variant v."""
+    if v <= 2:
+        return f"k_csr_stream<{1 << v}, false>"
+    if v >= 10:
+        return f"k_csr_stream<{1 << (v - 10)}, true>"
+    return f"k_spmv_plain<{1 << (v - 3)}>"
 
 
 def measured_traffic(name: str, kernel: str):
@@ -149,7 +162,12 @@ def run_spmv(args, torch, sable, synth, oracle):
     xd = torch.from_numpy(x).cuda()
     y = torch.empty(A.nrows, device="cuda")
     yp = torch.empty(A.nrows, device="cuda")
-    if args.autotune:
+    if args.variants:  # fixed kernels (profiling runs name the kernels the bench line chose)
+        hv, fs, pv = (int(v) for v in args.variants.split(","))
+        sable.sable_plan_set_variant(p, 0, hv)
+        sable.sable_plan_set_variant(p, 3, fs)
+        sable.sable_plan_set_variant(p, 2, pv)
+    elif args.autotune:
         sable.sable_autotune(p, 0, 1, xd, y)
     info = sable.sable_plan_info(p)
     f_h = lambda: sable.sable_spmv(p, xd, y)  # noqa: E731
@@ -165,6 +183,7 @@ def run_spmv(args, torch, sable, synth, oracle):
     cold_p = cold_launch_ms(f_p, 30, torch, flush)
     del flush
     nnz = A.nnz
+    kern = variant_kernel(info["spmv_variant"], info["far_split"])
     bytes_h = info["bytes_matrix"] + 4 * (A.nrows + A.ncols)
     bytes_p = 8 * nnz + 4 * (A.nrows + 1) + 4 * (A.nrows + A.ncols)
     ms = wall / args.steps * 1e3
@@ -180,11 +199,14 @@ def run_spmv(args, torch, sable, synth, oracle):
                    "vbr_tile": info["vbr_tile"], "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(f"spmv_{args.workload}", variant_kernel(info["spmv_variant"])),
-                     "kernel": variant_kernel(info["spmv_variant"]), "bytes_per_launch": bytes_h,
+                     "traffic": measured_traffic(f"spmv_{args.workload}", kern),
+                     "kernel": kern, "bytes_per_launch": bytes_h,
                      "launch_ms": round(ev_ms, 5)},
         "rel_err_fp64": err,
-        "plain_csr": {"gflops": round(2.0 * nnz / (wall_p / args.steps) / 1e9, 2),
+        "plain_csr": {"kernel": plain_kernel(info["plain_variant"]),
+                      "traffic": measured_traffic(f"spmv_{args.workload}_plain_csr",
+                                                  plain_kernel(info["plain_variant"])),
+                      "gflops": round(2.0 * nnz / (wall_p / args.steps) / 1e9, 2),
                       "launch_ms": round(ev_ms_p, 5), "rel_err_fp64": err_p,
                       "gbs": round(bytes_p / (ev_ms_p * 1e-3) / 1e9, 1)},
         "speedup_vs_plain_csr": round(ev_ms_p / ev_ms, 4),
@@ -194,7 +216,8 @@ def run_spmv(args, torch, sable, synth, oracle):
                  "speedup": round(cold_p / cold, 4)},
         "plan_ms": round(info["plan_ms"], 1), "plan_wall_s": round(plan_wall, 2),
         "partition": {k: info[k] for k in ("nseg", "vdia_nnz", "nblk", "vbr_nnz", "csr_nnz")},
-        "variants": {"hybrid": info["spmv_variant"], "plain": info["plain_variant"]},
+        "variants": {"hybrid": info["spmv_variant"], "far_split": info["far_split"],
+                     "far_nnz": info["far_nnz"], "plain": info["plain_variant"]},
     }
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")
@@ -360,6 +383,8 @@ def main():
     ap.add_argument("--plan", default="hybrid", choices=["hybrid", "vbr"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--variants", default="",
+                    help="SpMV: 'hybrid,far_split,plain' kernel variants instead of autotuning")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()

@@ -229,6 +229,18 @@ __global__ __launch_bounds__(kFarThreads) void k_far_gather(const int32_t* __res
   }
 }
 
+// The plain CSR baseline's streamed variants: the same tile body over the input as one CSR
+// matrix, under a kernel name of its own so profiles keep the two apart.
+template <int RPT, bool NT>
+__global__ __launch_bounds__(256) void k_csr_stream(PlanView P, const float* __restrict__ x,
+                                                   float* __restrict__ y) {
+  __shared__ float lds[kCsrChunk + kSpmvThreads * RPT];
+  int tile = xcd_tile(blockIdx.x, P.ntiles);
+  if (tile >= P.ntiles) return;
+  if (P.tile_order) tile = P.tile_order[tile];
+  spmv_tile_stream<RPT, NT>(P, tile, x, y, lds);
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void k_spmv_plain(const int32_t* __restrict__ ptr,
                                                    const int32_t* __restrict__ col,
@@ -394,24 +406,28 @@ void build_bf16_split(sable_plan_s& P, hipStream_t s) {
   LAUNCH_CHECK();
 }
 
-static void launch_stream(const PlanView& v, int rpt, bool nt, const float* x, float* y,
-                          hipStream_t s) {
-  const unsigned nb = (unsigned)(((v.ntiles + 7) / 8) * 8);
-  if (nt) {
-    switch (rpt) {
-      case 1: k_spmv_stream<1, true><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
-      case 2: k_spmv_stream<2, true><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
-      default: k_spmv_stream<4, true><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
-    }
-  } else {
-    switch (rpt) {
-      case 1: k_spmv_stream<1, false><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
-      case 2: k_spmv_stream<2, false><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
-      default: k_spmv_stream<4, false><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
-    }
+#define SABLE_STREAM_LAUNCH(KERNEL)                                                            \
+  static void launch_##KERNEL(const PlanView& v, int rpt, bool nt, const float* x, float* y,  \
+                              hipStream_t s) {                                                 \
+    const unsigned nb = (unsigned)(((v.ntiles + 7) / 8) * 8);                                  \
+    if (nt) {                                                                                  \
+      switch (rpt) {                                                                           \
+        case 1: KERNEL<1, true><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;                   \
+        case 2: KERNEL<2, true><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;                   \
+        default: KERNEL<4, true><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;                  \
+      }                                                                                        \
+    } else {                                                                                   \
+      switch (rpt) {                                                                           \
+        case 1: KERNEL<1, false><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;                  \
+        case 2: KERNEL<2, false><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;                  \
+        default: KERNEL<4, false><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;                 \
+      }                                                                                        \
+    }                                                                                          \
+    LAUNCH_CHECK();                                                                            \
   }
-  LAUNCH_CHECK();
-}
+SABLE_STREAM_LAUNCH(k_spmv_stream)
+SABLE_STREAM_LAUNCH(k_csr_stream)
+#undef SABLE_STREAM_LAUNCH
 
 void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
   const int var = P.prm.spmv_variant;
@@ -424,7 +440,7 @@ void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s)
           P.far.far_prod.p);
       LAUNCH_CHECK();
     }
-    launch_stream(v, 1 << k, var >= 8, x, y, s);
+    launch_k_spmv_stream(v, 1 << k, var >= 8, x, y, s);
     return;
   }
   const PlanView v = make_view(P, P.sched[0], false);
@@ -443,7 +459,7 @@ void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStrea
   const int var = P.prm.plain_variant;
   if (var <= 2 || var >= 10) {
     const int k = var <= 2 ? var : var - 10;
-    launch_stream(make_view(P, P.sched_plain[k], true), 1 << k, var >= 10, x, y, s);
+    launch_k_csr_stream(make_view(P, P.sched_plain[k], true), 1 << k, var >= 10, x, y, s);
     return;
   }
   const int W = 1 << (var - 3);

@@ -2,6 +2,7 @@
 // and keeps the fastest (lanes per CSR row for SpMV; the plain baseline gets the same
 // treatment so comparisons are against a tuned CSR kernel).
 #include <algorithm>
+#include <vector>
 
 #include "plan.h"
 
@@ -15,15 +16,27 @@ float time_ms(F&& f, hipStream_t s, int reps) {
   HIPC(hipEventCreate(&a));
   HIPC(hipEventCreate(&b));
   f();  // warm
-  HIPC(hipEventRecord(a, s));
-  for (int r = 0; r < reps; ++r) f();
-  HIPC(hipEventRecord(b, s));
-  HIPC(hipEventSynchronize(b));
-  float ms = 0.f;
-  HIPC(hipEventElapsedTime(&ms, a, b));
+  float r3[3];
+  for (int round = 0; round < 3; ++round) {
+    HIPC(hipEventRecord(a, s));
+    for (int r = 0; r < reps; ++r) f();
+    HIPC(hipEventRecord(b, s));
+    HIPC(hipEventSynchronize(b));
+    HIPC(hipEventElapsedTime(&r3[round], a, b));
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  return ms / reps;
+  std::sort(r3, r3 + 3);
+  return r3[1] / reps;  // median of three rounds
+}
+
+// Index of the variant to keep: the lowest-numbered one within 2% of the fastest, so that
+// near-ties resolve the same way from run to run.
+int pick(const std::vector<float>& t) {
+  const float best = *std::min_element(t.begin(), t.end());
+  for (size_t v = 0; v < t.size(); ++v)
+    if (t[v] <= 1.02f * best) return (int)v;
+  return 0;
 }
 
 }  // namespace
@@ -31,39 +44,37 @@ float time_ms(F&& f, hipStream_t s, int reps) {
 void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStream_t s) {
   const int reps = 10;
   if (op == 0) {
-    float best = 1e30f;
-    int bv = 0;
+    // hybrid SpMV: every variant without the far-column split, then the split for the
+    // chosen streamed variant (kept only if it wins by more than 2%)
+    const int far = P.prm.far_split;
+    P.prm.far_split = 0;
+    std::vector<float> t(11);
     for (int v = 0; v <= 10; ++v) {
       P.prm.spmv_variant = v;
-      float t = time_ms([&] { launch_spmv(P, x, y, s); }, s, reps);
-      if (t < best) { best = t; bv = v; }
+      t[v] = time_ms([&] { launch_spmv(P, x, y, s); }, s, reps);
     }
+    const int bv = pick(t);
     P.prm.spmv_variant = bv;
+    P.prm.far_split = far;
     if (P.far.npanel && (bv <= 2 || bv >= 8)) {
-      P.prm.far_split = 0;
-      const float t0 = time_ms([&] { launch_spmv(P, x, y, s); }, s, reps);
       P.prm.far_split = 1;
       const float t1 = time_ms([&] { launch_spmv(P, x, y, s); }, s, reps);
-      P.prm.far_split = t1 <= t0 ? 1 : 0;
+      P.prm.far_split = t1 * 1.02f < t[bv] ? 1 : 0;
     }
-    best = 1e30f;
-    bv = 0;
+    std::vector<float> tp(13);
     for (int v = 0; v <= 12; ++v) {
       P.prm.plain_variant = v;
-      float t = time_ms([&] { launch_spmv_plain(P, x, y, s); }, s, reps);
-      if (t < best) { best = t; bv = v; }
+      tp[v] = time_ms([&] { launch_spmv_plain(P, x, y, s); }, s, reps);
     }
-    P.prm.plain_variant = bv;
+    P.prm.plain_variant = pick(tp);
   } else {
     // x / y hold X (ncols x n) and Y (nrows x n)
-    float best = 1e30f;
-    int bm = 0;
+    std::vector<float> t(3);
     for (int m = 0; m <= 2; ++m) {
       P.prm.spmm_mode = m;
-      float t = time_ms([&] { launch_spmm(P, x, y, n, s); }, s, 3);
-      if (t < best) { best = t; bm = m; }
+      t[m] = time_ms([&] { launch_spmm(P, x, y, n, s); }, s, 2);
     }
-    P.prm.spmm_mode = bm;
+    P.prm.spmm_mode = pick(t);
   }
   HIPC(hipStreamSynchronize(s));
 }

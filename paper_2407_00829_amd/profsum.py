@@ -19,7 +19,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", "exec.h")]
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("exec.h", "exec.hip", "plan.h")]
 
 
 def kernel_source_sha() -> str:
@@ -42,12 +42,33 @@ def kernel_stats(trace_dir):
     return _csv(trace_dir, "kernel_stats.csv")
 
 
+def timed_mean_us(trace_dir, kernel, first, count):
+    """Mean duration of dispatches [first, first + count) of each named kernel (in launch
+    order), summed over the kernels of one product: the benchmark's timed region."""
+    rows = _csv(trace_dir, "kernel_trace.csv")
+    total = 0.0
+    for k in kernel.split(" + "):
+        d = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows
+                   if k in r["Kernel_Name"])
+        sel = d[first:first + count]
+        if len(sel) < count:
+            raise ValueError(f"only {len(d)} dispatches of {k!r}")
+        total += sum(e - b for b, e in sel) / len(sel) / 1e3
+    return total
+
+
 def counter_mean_kib(d, kernel):
-    vals = [float(r["Counter_Value"]) for r in _csv(d, "counter_collection.csv")
-            if kernel in r["Kernel_Name"]]
-    if not vals:
-        raise ValueError(f"kernel {kernel!r} not found under {d}")
-    return sum(vals) / len(vals), len(vals)
+    """Mean counter value per dispatch; kernel may name several kernels joined by ' + '
+    (one product launching each once), whose means are added."""
+    total, count = 0.0, None
+    rows = _csv(d, "counter_collection.csv")
+    for k in kernel.split(" + "):
+        vals = [float(r["Counter_Value"]) for r in rows if k in r["Kernel_Name"]]
+        if not vals:
+            raise ValueError(f"kernel {k!r} not found under {d}")
+        total += sum(vals) / len(vals)
+        count = len(vals) if count is None else min(count, len(vals))
+    return total, count
 
 
 def main(argv=None):
@@ -62,6 +83,9 @@ def main(argv=None):
     ap.add_argument("--fetch-copy", required=True)
     ap.add_argument("--write-copy", required=True)
     ap.add_argument("--cmd", required=True)
+    ap.add_argument("--timed", default="",
+                    help="'first,count': also report the mean over these dispatches of the "
+                         "kernel (the benchmark's timed launches)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args(argv)
     rows = kernel_stats(a.trace)
@@ -75,7 +99,8 @@ def main(argv=None):
     wf = half / (wc * 1024.0)
     fetch_b = f_k * 1024.0 * ff
     write_b = w_k * 1024.0 * wf
-    sel = [r for r in rows if a.kernel in r["Name"]]
+    parts = a.kernel.split(" + ")
+    sel = [[r for r in rows if k in r["Name"]] for k in parts]
     md = [f"# {a.name}: rocprofv3 kernel trace and HBM counters", "",
           "Commands (run from /tmp with TMPDIR=/tmp; DIR is an output directory):", "",
           f"    rocprofv3 --kernel-trace --stats --output-format csv -d DIR -o run -- {a.cmd}",
@@ -96,10 +121,20 @@ def main(argv=None):
            f"WRITE_SIZE reads {wc:.0f} KiB -> factor {wf:.3f}.",
            f"* Traffic per launch: fetched {fetch_b / 1e6:.1f} MB + written {write_b / 1e6:.1f} MB "
            f"= {(fetch_b + write_b) / 1e6:.1f} MB."]
-    if sel:
-        avg = float(sel[0]["AverageNs"]) / 1e3
+    if all(sel):
+        avgs = [float(r[0]["AverageNs"]) / 1e3 for r in sel]
+        avg = sum(avgs)
+        if len(avgs) > 1:
+            md.append("* Average durations " + " + ".join(f"{v:.2f}" for v in avgs) +
+                      f" = {avg:.2f} us per product.")
         md.append(f"* Average duration {avg:.2f} us -> {(fetch_b + write_b) / (avg * 1e-6) / 1e12:.2f} "
                   "TB/s of counted traffic.")
+        if a.timed:
+            first, count = (int(v) for v in a.timed.split(","))
+            tm = timed_mean_us(a.trace, a.kernel, first, count)
+            md.append(f"* Timed region (dispatches {first}..{first + count - 1} of the kernel, "
+                      f"after the warm-up and before the cache-cold launches): mean {tm:.2f} us -> "
+                      f"{(fetch_b + write_b) / (tm * 1e-6) / 1e12:.2f} TB/s of counted traffic.")
     os.makedirs(a.out, exist_ok=True)
     with open(os.path.join(a.out, f"{a.name}.md"), "w") as f:
         f.write("\n".join(md) + "\n")
