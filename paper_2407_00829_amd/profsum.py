@@ -71,7 +71,68 @@ def counter_mean_kib(d, kernel):
     return total, count
 
 
+def pmc_summary(argv):
+    """profsum pmc --name N --kernel K --dir DIR --trace DIR --cmd CMD --useful-flop F:
+    per-dispatch means of every counter collected for kernel K, with the matrix-core busy
+    fraction (sum of SQ_VALU_MFMA_BUSY_CYCLES over SIMDs / (GRBM_GUI_ACTIVE of one XCD x
+    SIMDs)) and MFMA FLOP (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512) when present."""
+    ap = argparse.ArgumentParser(prog="profsum pmc")
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--dir", required=True)
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--cmd", required=True)
+    ap.add_argument("--trace-cmd", required=True)
+    ap.add_argument("--simds", type=int, default=256 * 4)
+    ap.add_argument("--xcds", type=int, default=8)
+    ap.add_argument("--useful-flop", type=float, default=0.0,
+                    help="algorithmic FLOP of one dispatch (2 nnz n x 3 products)")
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    a = ap.parse_args(argv)
+    rows = [r for r in _csv(a.dir, "counter_collection.csv") if a.kernel in r["Kernel_Name"]]
+    if not rows:
+        raise ValueError(f"kernel {a.kernel!r} not found under {a.dir}")
+    by = {}
+    for r in rows:
+        by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    mean = {k: sum(v) / len(v) for k, v in by.items()}
+    st = [r for r in kernel_stats(a.trace) if a.kernel in r["Name"]]
+    avg_us = float(st[0]["AverageNs"]) / 1e3 if st else 0.0
+    md = [f"# {a.name}: rocprofv3 counters of `{a.kernel}`", "",
+          "Commands (run from /tmp with TMPDIR=/tmp; DIR is an output directory):", "",
+          f"    rocprofv3 --pmc {' '.join(sorted(mean))} --output-format csv -d DIR -o run -- {a.cmd}",
+          f"    rocprofv3 --kernel-trace --stats --output-format csv -d DIR -o run -- {a.trace_cmd}", "",
+          "| counter | mean per dispatch |", "|---|---|"]
+    for k in sorted(mean):
+        md.append(f"| {k} | {mean[k]:.6g} |")
+    md.append("")
+    if st:
+        md.append(f"* Kernel-trace average duration: {avg_us:.1f} us over {st[0]['Calls']} dispatches.")
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in mean and "GRBM_GUI_ACTIVE" in mean:
+        gui = mean["GRBM_GUI_ACTIVE"] / a.xcds  # one XCD's active cycles
+        util = mean["SQ_VALU_MFMA_BUSY_CYCLES"] / (gui * a.simds)
+        md.append(f"* Matrix-core busy fraction: {mean['SQ_VALU_MFMA_BUSY_CYCLES']:.4g} / "
+                  f"({gui:.4g} x {a.simds}) = {100 * util:.2f}%.")
+    if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in mean:
+        fl = mean["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512
+        md.append(f"* BF16 MFMA work issued: {fl / 1e9:.1f} GFLOP per dispatch"
+                  + (f" ({fl / (avg_us * 1e-6) / 1e12:.1f} TFLOP/s at the traced duration)" if avg_us else "")
+                  + ".")
+        if a.useful_flop:
+            md.append(f"* Algorithmic split-bf16 work {a.useful_flop / 1e9:.1f} GFLOP: "
+                      f"{100 * a.useful_flop / fl:.1f}% of the issued MFMA work is useful "
+                      "(the rest is zero padding of the blocks to 16x16x16 steps).")
+    os.makedirs(a.out, exist_ok=True)
+    with open(os.path.join(a.out, f"{a.name}.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def main(argv=None):
+    import sys
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "pmc":
+        return pmc_summary(argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--name", required=True)
     ap.add_argument("--kernel", required=True)
