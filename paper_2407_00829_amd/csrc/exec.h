@@ -38,11 +38,6 @@ struct PlanView {
 // far = true: the view with the far-column split, if the plan has one and it is enabled.
 PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool far = false);
 
-// CSR term k of the view: a[k] * x[col[k]], or the precomputed far product.
-__device__ __forceinline__ float csr_term(const PlanView& P, int j, float a, const float* __restrict__ x) {
-  if (j >= 0) return a * x[j];
-  return P.far_prod[-j - 1];
-}
 
 // ---- SpMV tile body --------------------------------------------------------------------
 // blockDim.x == rows_per_tile threads; thread t owns row tile*rows_per_tile + t for the band
@@ -144,22 +139,36 @@ __device__ __forceinline__ T ld(const T* p) {
   else return *p;
 }
 
-// One CSR pass: thread t takes entries e0 + t + 256*u (u < U) below e_end.
+// One CSR pass: thread t takes entries e0 + t + 256*u (u < U) below e_end (e0 < e_end).
+// csr_issue loads columns, values and the gathered operands; csr_finish forms the products
+// later, so other loads can be issued while the gathers are in flight. Indices past e_end
+// load entry e_end - 1 again and contribute 0, so every load is unconditional.
+template <int U>
+struct CsrFlight {
+  int j[U];
+  float a[U], v[U];
+};
+
 template <bool NT, int U>
-__device__ __forceinline__ void csr_pass(const PlanView& P, int e0, int e_end,
-                                         const float* __restrict__ x, float (&pv)[U]) {
-  int jj[U];
-  float aa[U];
+__device__ __forceinline__ void csr_issue(const PlanView& P, int e0, int e_end,
+                                          const float* __restrict__ x, CsrFlight<U>& f) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int k = e0 + (int)threadIdx.x + kSpmvThreads * u;
-    jj[u] = k < e_end ? ld<NT>(P.csr_col + k) : 0;
-    aa[u] = k < e_end ? ld<NT>(P.csr_val + k) : 0.f;
+    const int k = min(e0 + (int)threadIdx.x + kSpmvThreads * u, e_end - 1);
+    f.j[u] = ld<NT>(P.csr_col + k);
+    f.a[u] = ld<NT>(P.csr_val + k);
   }
+  const float* fp = P.far_prod ? P.far_prod : x;
+#pragma unroll
+  for (int u = 0; u < U; ++u) f.v[u] = *(f.j[u] >= 0 ? x + f.j[u] : fp + (-1 - f.j[u]));
+}
+
+template <int U>
+__device__ __forceinline__ void csr_finish(const CsrFlight<U>& f, int e0, int e_end, float (&pv)[U]) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int k = e0 + (int)threadIdx.x + kSpmvThreads * u;
-    pv[u] = k < e_end ? csr_term(P, jj[u], aa[u], x) : 0.f;
+    const float pr = f.j[u] >= 0 ? f.a[u] * f.v[u] : f.v[u];
+    pv[u] = e0 + (int)threadIdx.x + kSpmvThreads * u < e_end ? pr : 0.f;
   }
 }
 
@@ -196,8 +205,8 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
     svp = P.seg_val_ptr[slo];
     sip = P.seg_idiag_ptr[slo];
   }
-  float pv[U];
-  csr_pass<NT, U>(P, e_begin, e_end, x, pv);
+  CsrFlight<U> fl;
+  if (e_begin < e_end) csr_issue<NT, U>(P, e_begin, e_end, x, fl);
 
   float acc[RPT];
 #pragma unroll
@@ -224,8 +233,9 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
         int c[4];
         bool ok[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          c[u] = d + u < cnd ? r + od[d + u] : -1;
+        for (int u = 0; u < 4; ++u) {  // offsets past the segment's last read it again
+          const int o = od[min(d + u, cnd - 1)];
+          c[u] = d + u < cnd ? r + o : -1;
           ok[u] = (unsigned)c[u] < (unsigned)P.ncols;
         }
         float vv[4], xv[4];
@@ -296,8 +306,10 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
   float cs[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) cs[q] = 0.f;
+  float pv[U];
   for (int e0 = e_begin; e0 < e_end; e0 += kPass) {
-    if (e0 != e_begin) csr_pass<NT, U>(P, e0, e_end, x, pv);
+    if (e0 != e_begin) csr_issue<NT, U>(P, e0, e_end, x, fl);
+    csr_finish<U>(fl, e0, e_end, pv);
     const int n = min(kPass, e_end - e0);
     __syncthreads();  // previous pass's row sums are done with prod
 #pragma unroll
