@@ -177,7 +177,7 @@ sable_status sable_plan_export(sable_plan_t p, const sable_partition_host* out);
  * so results are bitwise reproducible. x[ncols], y[nrows] device fp32.
  * Far-column split: for wide matrices (more than 2^20 columns) whose CSR part has at least
  * 2^16 entries more than 2^17 columns away from their row, the streamed variants first run
- * a gather pass over those entries (grouped by 16384-column slices of x, each staged in
+ * a gather pass over those entries (grouped by 8192-column slices of x, each staged in
  * LDS) into a product buffer owned by the plan, then the fused launch adds the products
  * in the same order as without the pass. Two calls with the same plan must therefore not
  * run concurrently on different streams. */

@@ -46,7 +46,7 @@ struct ExecParams {
 // takes the stored product for it. The order of every row's sum is unchanged, so results
 // equal those without the split bit for bit.
 constexpr int kFarWindow = 1 << 17;      // |column - row| above this is far
-constexpr int kFarPanelCols = 1 << 14;   // x slice per panel: 64 KB of fp32 in LDS
+constexpr int kFarPanelCols = 1 << 13;   // x slice per panel: 32 KB of fp32 in LDS
 constexpr int kFarThreads = 512;
 constexpr int kFarChunk = 8 * kFarThreads;  // entries per gather workgroup
 constexpr int kFarMinEntries = 1 << 16;  // below this the extra pass is not worth a launch
