@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_spmv_plain(const int32_t* __restrict__ 
   csr_rows<W>(ptr, col, val, nrows, x, y, blockIdx.x * rows_per_block, rows_per_block);
 }
 
-__global__ __launch_bounds__(kMmThreads) void k_spmm_tile(PlanView P, const float* __restrict__ X,
+__global__ __launch_bounds__(kMmThreads, 4) void k_spmm_tile(PlanView P, const float* __restrict__ X,
                                                          float* __restrict__ Y, int n, int use_mfma) {
   __shared__ float ys[kMmRows * kMmCols + kMmBlkStage * kBlkDesc];
   const int ntile = (P.nrows + kMmRows - 1) / kMmRows;

@@ -26,6 +26,7 @@ constexpr int kMmCols = 128;
 constexpr int kMmThreads = 256;
 constexpr int kMmBlkStage = 256;  // block descriptors staged in LDS per pass
 constexpr int kBlkDesc = 8;       // ints per staged descriptor
+constexpr int kMmBatch = 3;       // small blocks whose operand loads are issued together
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
@@ -38,6 +39,22 @@ __device__ __forceinline__ uint16_t bf16_rne_dev(float f) {
 }
 
 __device__ __forceinline__ float bf16_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+typedef __bf16 bf16x2v_t __attribute__((ext_vector_type(2)));
+typedef float float2v_t __attribute__((ext_vector_type(2)));
+
+// Split four fp32 values into bf16 hi and lo parts (x = hi + lo + O(2^-16 |x|)) with the
+// hardware round-to-nearest-even conversion, two values per instruction.
+__device__ __forceinline__ void split4(const float (&x)[4], bf16x4_t& hi, bf16x4_t& lo) {
+  const uint32_t h01 = __builtin_bit_cast(uint32_t, __builtin_convertvector(float2v_t{x[0], x[1]}, bf16x2v_t));
+  const uint32_t h23 = __builtin_bit_cast(uint32_t, __builtin_convertvector(float2v_t{x[2], x[3]}, bf16x2v_t));
+  const float2v_t r01 = {x[0] - __uint_as_float(h01 << 16), x[1] - __uint_as_float(h01 & 0xffff0000u)};
+  const float2v_t r23 = {x[2] - __uint_as_float(h23 << 16), x[3] - __uint_as_float(h23 & 0xffff0000u)};
+  const uint32_t l01 = __builtin_bit_cast(uint32_t, __builtin_convertvector(r01, bf16x2v_t));
+  const uint32_t l23 = __builtin_bit_cast(uint32_t, __builtin_convertvector(r23, bf16x2v_t));
+  hi = __builtin_bit_cast(bf16x4_t, make_uint2(h01, h23));
+  lo = __builtin_bit_cast(bf16x4_t, make_uint2(l01, l23));
+}
 
 // Copy nq block descriptors of the tile list (starting at q0) into LDS, all threads.
 __device__ __forceinline__ void stage_blocks(const PlanView& P, int q0, int nq, int* sb) {
@@ -57,6 +74,82 @@ __device__ __forceinline__ void stage_blocks(const PlanView& P, int q0, int nq, 
     d[7] = (int)(uint32_t)((uint64_t)mp >> 32);
   }
   __syncthreads();
+}
+
+// Three split-bf16 products of one 16x16x16 step into acc[0..1] (the wave's two column
+// chunks): a = packed hi|lo words of this lane's four k values, b = X fragments.
+__device__ __forceinline__ void mfma3(floatx4_t (&acc)[2], const uint4& aw, const bf16x4_t (&bh)[2],
+                                      const bf16x4_t (&bl)[2], int wave, int nc) {
+  bf16x4_t ah, al;
+  ah[0] = (short)(aw.x & 0xffffu); al[0] = (short)(aw.x >> 16);
+  ah[1] = (short)(aw.y & 0xffffu); al[1] = (short)(aw.y >> 16);
+  ah[2] = (short)(aw.z & 0xffffu); al[2] = (short)(aw.z >> 16);
+  ah[3] = (short)(aw.w & 0xffffu); al[3] = (short)(aw.w >> 16);
+#pragma unroll
+  for (int ci = 0; ci < 2; ++ci) {
+    if ((wave + 4 * ci) * 16 >= nc) continue;
+    acc[ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[ci], acc[ci], 0, 0, 0);
+    acc[ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[ci], acc[ci], 0, 0, 0);
+    acc[ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[ci], acc[ci], 0, 0, 0);
+  }
+}
+
+// cnt (1..kMmBatch) items: k step ik[s] (a multiple of 16) of staged block sb[ib[s]], each
+// block overlapping at most two consecutive 16-row slices of the tile. Every operand load of
+// the batch is issued first, then the products run item by item (slices ascending), the
+// order of the general path.
+__device__ __forceinline__ void mfma_small_batch(const PlanView& P, const int* sb, const int (&ib)[kMmBatch],
+                                                 const int (&ik)[kMmBatch],
+                                                 int cnt, int r0, int rend, int cb, int n, int nc,
+                                                 const float* __restrict__ X, int wave, int m, int kg,
+                                                 floatx4_t (&acc)[4][2]) {
+  float xr[kMmBatch][2][4];
+  uint4 aw[kMmBatch][2];
+  int ma[kMmBatch], nsl[kMmBatch];
+#pragma unroll
+  for (int s = 0; s < kMmBatch; ++s) {
+    const bool sv = s < cnt;
+    const int* d = sb + kBlkDesc * ib[sv ? s : 0];
+    const int k0 = ik[sv ? s : 0];
+    const int br0 = d[0], c0 = d[2], w = d[3] - d[2];
+    const int w4 = (w + 3) & ~3;
+    const int lo = max(br0, r0), hi = min(d[1], rend);
+    const i64 mp = (i64)(((uint64_t)(uint32_t)d[7] << 32) | (uint32_t)d[6]);
+    ma[s] = (lo - r0) >> 4;
+    nsl[s] = sv ? ((hi - 1 - r0) >> 4) - ma[s] + 1 : 0;
+    // every load is issued (addresses clamped into the block and into X) and masked after
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = k0 + 4 * kg + i;
+      const float* xrow = X + (i64)(c0 + min(k, w - 1)) * n + cb;
+#pragma unroll
+      for (int ci = 0; ci < 2; ++ci) {
+        const int col = (wave + 4 * ci) * 16 + m;
+        xr[s][ci][i] = xrow[min(col, nc - 1)];
+        if (!(sv && col < nc && k < w)) xr[s][ci][i] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int arow = r0 + 16 * (ma[s] + sl) + m;
+      const int ar = min(max(arow, lo), hi - 1), ak = min(k0 + 4 * kg, w4 - 4);
+      aw[s][sl] = *reinterpret_cast<const uint4*>(P.vbr_mma + mp + (i64)(ar - br0) * w4 + ak);
+      if (!(sl < nsl[s] && arow >= lo && arow < hi && k0 + 4 * kg < w4)) aw[s][sl] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kMmBatch; ++s) {
+    if (s >= cnt) break;
+    bf16x4_t bh[2], bl[2];
+#pragma unroll
+    for (int ci = 0; ci < 2; ++ci) split4(xr[s][ci], bh[ci], bl[ci]);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {  // slices ascending; ma[s] is wave-uniform
+      const int sl = mt - ma[s];
+      if (sl < 0 || sl >= nsl[s]) continue;
+      mfma3(acc[mt], sl == 0 ? aw[s][0] : aw[s][1], bh, bl, wave, nc);
+    }
+  }
 }
 
 // Rows [r0, r0+kMmRows) x columns [cb, cb+nc) of Y. lds = kMmRows x kMmCols floats for the
@@ -119,55 +212,72 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
     for (int q0 = blo; q0 < bhi; q0 += kMmBlkStage) {
      const int nq = min(kMmBlkStage, bhi - q0);
      stage_blocks(P, q0, nq, sb);
-     for (int j = 0; j < nq; ++j) {
-      const int* dsc = sb + kBlkDesc * j;
+     int j = 0, kstart = 0;  // next block and its next 16-wide k step
+     while (j < nq) {
+      // up to kMmBatch (block, k step) items of blocks overlapping at most two 16-row
+      // slices of the tile go together: all their operand loads are issued before any of
+      // their products, which then run in (block, k step, slice) order as in the general
+      // path below
+      int ib[kMmBatch], ik[kMmBatch];
+      int cnt = 0, jj = j, kk0 = kstart;
+      while (cnt < kMmBatch && jj < nq) {
+        const int* d = sb + kBlkDesc * jj;
+        const int lo = max(d[0], r0), hi = min(d[1], rend);
+        if (lo >= hi) { ++jj; kk0 = 0; continue; }
+        if (((hi - 1 - r0) >> 4) - ((lo - r0) >> 4) > 1) break;
+        ib[cnt] = jj;
+        ik[cnt] = kk0;
+        ++cnt;
+        kk0 += 16;
+        if (kk0 >= d[3] - d[2]) { ++jj; kk0 = 0; }
+      }
+      if (cnt > 0) {
+        mfma_small_batch(P, sb, ib, ik, cnt, r0, rend, cb, n, nc, X, wave, m, kg, acc);
+        j = jj;
+        kstart = kk0;
+        continue;
+      }
+      if (jj >= nq) break;
+      // general block jj: any width and height
+      const int* dsc = sb + kBlkDesc * jj;
+      j = jj + 1;
+      kstart = 0;
       const int br0 = dsc[0], br1 = dsc[1];
       const int lo = max(br0, r0), hi = min(br1, rend);
-      if (lo >= hi) continue;
       const int c0 = dsc[2], c1 = dsc[3];
       const int w = c1 - c0, w4 = (w + 3) & ~3;
       const i64 mp = (i64)(((uint64_t)(uint32_t)dsc[7] << 32) | (uint32_t)dsc[6]);
       for (int k0 = 0; k0 < w; k0 += 16) {
         const int kk = k0 + 4 * kg;  // first of this lane's four k values
         // B fragments (both column chunks) and A fragments (every 16-row slice) first
-        bf16x4_t bh[2], bl[2];
+        // every load is issued (addresses clamped into the block and into X), masked after
+        float xr[2][4];
 #pragma unroll
         for (int ci = 0; ci < 2; ++ci) {
           const int col = (wave + 4 * ci) * 16 + m;
-          const bool cok = col < nc;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int k = kk + i;
-            const float xv = (cok && k < w) ? X[(i64)(c0 + k) * n + cb + col] : 0.f;
-            const uint16_t xh = bf16_rne_dev(xv);
-            bh[ci][i] = (short)xh;
-            bl[ci][i] = (short)bf16_rne_dev(xv - bf16_f32(xh));
+            xr[ci][i] = X[(i64)(c0 + min(k, w - 1)) * n + cb + min(col, nc - 1)];
+            if (!(col < nc && k < w)) xr[ci][i] = 0.f;
           }
         }
         uint4 aw[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
           const int arow = r0 + 16 * mt + m;
-          aw[mt] = make_uint4(0u, 0u, 0u, 0u);
-          if (arow >= lo && arow < hi && kk < w4)
-            aw[mt] = *reinterpret_cast<const uint4*>(P.vbr_mma + mp + (i64)(arow - br0) * w4 + kk);
+          const int ar = min(max(arow, lo), hi - 1), ak = min(kk, w4 - 4);
+          aw[mt] = *reinterpret_cast<const uint4*>(P.vbr_mma + mp + (i64)(ar - br0) * w4 + ak);
+          if (!(arow >= lo && arow < hi && kk < w4)) aw[mt] = make_uint4(0u, 0u, 0u, 0u);
         }
+        bf16x4_t bh[2], bl[2];
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci) split4(xr[ci], bh[ci], bl[ci]);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
           const int m0 = r0 + 16 * mt;
           if (m0 >= hi || m0 + 16 <= lo) continue;
-          bf16x4_t ah, al;
-          ah[0] = (short)(aw[mt].x & 0xffffu); al[0] = (short)(aw[mt].x >> 16);
-          ah[1] = (short)(aw[mt].y & 0xffffu); al[1] = (short)(aw[mt].y >> 16);
-          ah[2] = (short)(aw[mt].z & 0xffffu); al[2] = (short)(aw[mt].z >> 16);
-          ah[3] = (short)(aw[mt].w & 0xffffu); al[3] = (short)(aw[mt].w >> 16);
-#pragma unroll
-          for (int ci = 0; ci < 2; ++ci) {
-            if ((wave + 4 * ci) * 16 >= nc) continue;
-            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[ci], acc[mt][ci], 0, 0, 0);
-            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[ci], acc[mt][ci], 0, 0, 0);
-            acc[mt][ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[ci], acc[mt][ci], 0, 0, 0);
-          }
+          mfma3(acc[mt], aw[mt], bh, bl, wave, nc);
         }
       }
      }
@@ -222,20 +332,27 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
     float a0 = 0.f, a1 = 0.f;
     const int ke = P.csr_ptr[r + 1];
     int k = P.csr_ptr[r];
-    // eight X rows in flight per lane
+    // eight X rows in flight per lane: indices and values first, then every X load
+    // (columns clamped into the chunk, masked when used)
+    const int cAc = min(cA, nc - 1), cBc = min(cB, nc - 1);
     for (; k + 8 <= ke; k += 8) {
+      int cc[8];
       float va[8], xa[8], xb[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
+        cc[u] = P.csr_col[k + u];
         va[u] = P.csr_val[k + u];
-        const float* xr = X + (i64)P.csr_col[k + u] * n + cb;
-        xa[u] = okA ? xr[cA] : 0.f;
-        xb[u] = okB ? xr[cB] : 0.f;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        a0 += va[u] * xa[u];
-        a1 += va[u] * xb[u];
+        const float* xr = X + (i64)cc[u] * n + cb;
+        xa[u] = xr[cAc];
+        xb[u] = xr[cBc];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a0 += va[u] * (okA ? xa[u] : 0.f);
+        a1 += va[u] * (okB ? xb[u] : 0.f);
       }
     }
     for (; k < ke; ++k) {
