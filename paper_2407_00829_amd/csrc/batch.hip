@@ -34,19 +34,20 @@ __global__ void k_batch_reset(unsigned* __restrict__ counter, unsigned* __restri
 constexpr int kBatchLds = kMmRows * kMmCols + kMmBlkStage * kBlkDesc;  // >= largest SpMV tile
 static_assert(kBatchLds >= kCsrChunk + 1024, "LDS budget");
 
-__global__ __launch_bounds__(256) void k_batch(const PlanView* __restrict__ views,
+__global__ __launch_bounds__(256, 3) void k_batch(const PlanView* __restrict__ views,
                                                const BatchItemDev* __restrict__ items,
                                                const i64* __restrict__ unit_off, int count,
                                                i64 total, unsigned* __restrict__ counter,
                                                unsigned* __restrict__ done,
                                                unsigned long long* __restrict__ stamps) {
-  __shared__ float lds[kBatchLds];
-  __shared__ i64 unit;
+  __shared__ float lds[kBatchLds];  // exactly 40 KB: four workgroups per CU
+  unsigned* unit = reinterpret_cast<unsigned*>(lds);  // broadcast slot, free between units
   for (;;) {
+    __syncthreads();  // the previous unit is done with the LDS
+    if (threadIdx.x == 0) unit[0] = atomicAdd(counter, 1u);
     __syncthreads();
-    if (threadIdx.x == 0) unit = (i64)atomicAdd(counter, 1u);
-    __syncthreads();
-    const i64 u = unit;
+    const i64 u = (i64)unit[0];
+    __syncthreads();  // every thread has read the slot before the unit body reuses it
     if (u >= total) break;
     int lo = 0, hi = count - 1;  // item of unit u
     while (lo < hi) {
@@ -164,7 +165,9 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
     HIPC(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIPC(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     B->tick_hz = (double)khz * 1e3;
-    const unsigned grid = (unsigned)std::max<i64>(1, std::min<i64>(total, (i64)cus * 4));
+    int per_cu = 0;  // resident workgroups per CU for this kernel (registers and LDS)
+    HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, 256, 0));
+    const unsigned grid = (unsigned)std::max<i64>(1, std::min<i64>(total, (i64)cus * std::max(1, per_cu)));
     HIPC(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
     HIPC(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
     k_batch_reset<<<1, 256, 0, B->cap>>>(B->counter.p, B->done.p, count, B->stamps.p);
