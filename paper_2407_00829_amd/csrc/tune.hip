@@ -44,23 +44,28 @@ int pick(const std::vector<float>& t) {
 void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStream_t s) {
   const int reps = 10;
   if (op == 0) {
-    // hybrid SpMV: every variant without the far-column split, then the split for the
-    // chosen streamed variant (kept only if it wins by more than 2%)
-    const int far = P.prm.far_split;
+    // hybrid SpMV: every variant without the far-column split, then every streamed variant
+    // with it; candidates are ranked in that order, so the split is kept only where it is
+    // more than 2% faster than every variant without it
+    std::vector<float> t;
+    std::vector<std::pair<int, int>> cand;  // (variant, far split)
     P.prm.far_split = 0;
-    std::vector<float> t(11);
     for (int v = 0; v <= 10; ++v) {
       P.prm.spmv_variant = v;
-      t[v] = time_ms([&] { launch_spmv(P, x, y, s); }, s, reps);
+      t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
+      cand.push_back({v, 0});
     }
-    const int bv = pick(t);
-    P.prm.spmv_variant = bv;
-    P.prm.far_split = far;
-    if (P.far.npanel && (bv <= 2 || bv >= 8)) {
+    if (P.far.npanel) {
       P.prm.far_split = 1;
-      const float t1 = time_ms([&] { launch_spmv(P, x, y, s); }, s, reps);
-      P.prm.far_split = t1 * 1.02f < t[bv] ? 1 : 0;
+      for (int v : {0, 1, 2, 8, 9, 10}) {
+        P.prm.spmv_variant = v;
+        t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
+        cand.push_back({v, 1});
+      }
     }
+    const int c = pick(t);
+    P.prm.spmv_variant = cand[c].first;
+    P.prm.far_split = cand[c].second;
     std::vector<float> tp(13);
     for (int v = 0; v <= 12; ++v) {
       P.prm.plain_variant = v;

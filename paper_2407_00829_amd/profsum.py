@@ -128,11 +128,45 @@ def pmc_summary(argv):
     print("\n".join(md))
 
 
+def trace_summary(argv):
+    """profsum trace --name N --trace DIR --cmd CMD [--kernel K --flop F]: the kernel-trace
+    stats table, and for kernel K its average duration and FLOP rate at F FLOP per dispatch."""
+    ap = argparse.ArgumentParser(prog="profsum trace")
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--cmd", required=True)
+    ap.add_argument("--kernel", default="")
+    ap.add_argument("--flop", type=float, default=0.0)
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    a = ap.parse_args(argv)
+    rows = kernel_stats(a.trace)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    md = [f"# {a.name}: rocprofv3 kernel trace", "",
+          "Command (run from /tmp with TMPDIR=/tmp; DIR is an output directory):", "",
+          f"    rocprofv3 --kernel-trace --stats --output-format csv -d DIR -o run -- {a.cmd}", "",
+          "| kernel | calls | average us | min us | max us |", "|---|---|---|---|---|"]
+    for r in rows[:12]:
+        md.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                  f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
+    sel = [r for r in rows if a.kernel and a.kernel in r["Name"]]
+    if sel:
+        avg = float(sel[0]["AverageNs"]) / 1e3
+        md += ["", f"* `{a.kernel}`: average {avg:.1f} us over {sel[0]['Calls']} dispatches"
+               + (f"; {a.flop / 1e9:.1f} GFLOP per dispatch -> {a.flop / (avg * 1e-6) / 1e12:.2f} TFLOP/s."
+                  if a.flop else ".")]
+    os.makedirs(a.out, exist_ok=True)
+    with open(os.path.join(a.out, f"{a.name}.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def main(argv=None):
     import sys
     argv = sys.argv[1:] if argv is None else argv
     if argv and argv[0] == "pmc":
         return pmc_summary(argv[1:])
+    if argv and argv[0] == "trace":
+        return trace_summary(argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--name", required=True)
     ap.add_argument("--kernel", required=True)
