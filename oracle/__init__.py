@@ -8,6 +8,8 @@ Functions (each follows the passage cited in oracle/sor.cpp):
   plan(A, kinds, vbr_mode, th)   extractors in list order (Sec. 3, Alg. 1-4) -> dict of arrays
   spmv(A, x), spmm(A, X)         FP64 products over A's entries (Sec. 5 "Kernels")
   spmv_rows / spmm_rows          the same for selected rows (sampled checks at full size)
+  spmv64(A, v, x), spmm64(A, v, X)  FP64 products with fp64 values and operands (the
+                                 paper's precision, Sec. 5 / App. A), entries in CSR order
   partition_spmv(h, x)           FP64 product over a plan's formats (fill included)
   bf16_split(a)                  round-to-nearest-even hi/lo split of fp32 values
   rel_err(y, yref)               normwise relative error ||y - yref||_2 / ||yref||_2
@@ -236,6 +238,28 @@ def spmm(A, X: np.ndarray) -> np.ndarray:
     n = X.shape[1]
     Y = np.zeros((A.nrows, n), np.float64)
     lib.sor_spmm_f64(A.nrows, _p(ip), _p(ix), _p(vv), _p(X), n, _p(Y))
+    return Y
+
+
+def spmv64(A, values: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """y[i] = sum over A's stored entries (i, j) of values[k] * x[j], all in FP64; values are
+    given in A's CSR order (the plan's input order) and replace A.values. Entries are added
+    in CSR order."""
+    rows = np.repeat(np.arange(A.nrows, dtype=np.int64), np.diff(np.asarray(A.indptr, np.int64)))
+    v = np.asarray(values, np.float64)
+    xd = np.asarray(x, np.float64)
+    y = np.zeros(A.nrows, np.float64)
+    np.add.at(y, rows, v * xd[np.asarray(A.indices, np.int64)])
+    return y
+
+
+def spmm64(A, values: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Y = A X in FP64 with fp64 values (CSR order) and a row-major fp64 X."""
+    rows = np.repeat(np.arange(A.nrows, dtype=np.int64), np.diff(np.asarray(A.indptr, np.int64)))
+    v = np.asarray(values, np.float64)
+    Xd = np.asarray(X, np.float64)
+    Y = np.zeros((A.nrows, Xd.shape[1]), np.float64)
+    np.add.at(Y, rows, v[:, None] * Xd[np.asarray(A.indices, np.int64)])
     return Y
 
 

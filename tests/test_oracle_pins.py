@@ -326,6 +326,25 @@ def test_spmv_spmm_brute_force(seed):
     assert np.array_equal(oracle.spmm_rows(A, X, rows), oracle.spmm(A, X)[rows])
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_fp64_input_products_brute_force(seed):
+    """spmv64 / spmm64 (fp64 values and operands, not representable in fp32) equal the dense
+    FP64 product on rectangular matrices with empty rows, within FP64 rounding."""
+    A = gen_random_small(seed, 41 + seed, 29, 0.1, nbands=1, nblocks=1)
+    rng = np.random.default_rng(100 + seed)
+    v = rng.standard_normal(A.nnz) * (1.0 + 1e-12 * rng.standard_normal(A.nnz))
+    D = np.zeros((A.nrows, A.ncols), np.float64)
+    D[A.rows(), A.indices] = v
+    x = rng.standard_normal(A.ncols)
+    X = rng.standard_normal((A.ncols, 7))
+    assert np.allclose(oracle.spmv64(A, v, x), D @ x, rtol=0, atol=1e-13)
+    assert np.allclose(oracle.spmm64(A, v, X), D @ X, rtol=0, atol=1e-13)
+    # the fp32-input oracle is the special case of fp32-representable values
+    x32 = x.astype(np.float32)
+    assert np.allclose(oracle.spmv64(A, A.values.astype(np.float64), x32.astype(np.float64)),
+                       oracle.spmv(A, x32), rtol=0, atol=1e-13)
+
+
 # --- exact cover on random matrices (Sec. 3 completeness) ------------------------------
 
 PLANS = [[C], [V, C], [B, C], [V, B, C], [B, V, C]]
