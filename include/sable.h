@@ -192,6 +192,19 @@ sable_status sable_spmm(sable_plan_t p, const float* X, float* Y, int32_t n, voi
  * row) applied to A. Equivalent to a plan with list {CSR}; provided for comparisons. */
 sable_status sable_csr_spmv(sable_plan_t p, const float* x, float* y, void* stream);
 
+/* ---- FP64 executor (the paper's precision, Sec. 5 / App. A) -------------------------
+ * The partition depends only on the structure, so an fp32 plan also serves fp64 products:
+ * sable_update_values_f64 stores fp64 values (device values[nnz], input order, same
+ * structure as at planning time) in fp64 copies of every format (allocated on the first
+ * call, asynchronous on `stream`). sable_spmv_f64 / sable_spmm_f64 then run the same fused
+ * tile bodies in fp64 (VBR blocks on the fp64 VALU: gfx950's fp64 matrix-core peak equals
+ * its fp64 vector peak); x[ncols], y[nrows], X[ncols x n], Y[nrows x n] device fp64,
+ * row-major. Summation orders are fixed as in the fp32 executor (bitwise reproducible).
+ * Both return SABLE_ERR_INVALID_ARG until fp64 values have been set. */
+sable_status sable_update_values_f64(sable_plan_t p, const double* values, void* stream);
+sable_status sable_spmv_f64(sable_plan_t p, const double* x, double* y, void* stream);
+sable_status sable_spmm_f64(sable_plan_t p, const double* X, double* Y, int32_t n, void* stream);
+
 /* ||y - yref||_2 / ||yref||_2 (or ||y - yref||_2 if yref = 0) reduced in FP64 on the GPU:
  * y[len] fp32 device, yref[len] fp64 device, *out host. Synchronises `stream`. */
 sable_status sable_error_norm_f64(const float* y, const double* yref, int64_t len,

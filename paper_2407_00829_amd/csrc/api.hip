@@ -37,19 +37,21 @@ __global__ void k_csr_owner(const int32_t* __restrict__ rid, i64 n, int8_t* __re
   }
 }
 
-// Refresh every stored value from a new value array with the same structure.
-__global__ void k_update_values(const float* __restrict__ values, i64 nnz,
+// Refresh every stored value from a new value array with the same structure (aval: the
+// whole-input copy, may be null).
+template <class T>
+__global__ void k_update_values(const T* __restrict__ values, i64 nnz,
                                 const int8_t* __restrict__ owner, const i64* __restrict__ slot,
-                                float* __restrict__ vdia, float* __restrict__ vbr,
-                                float* __restrict__ csr, float* __restrict__ aval) {
+                                T* __restrict__ vdia, T* __restrict__ vbr, T* __restrict__ csr,
+                                T* __restrict__ aval) {
   for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < nnz; k += (i64)gridDim.x * blockDim.x) {
-    const float v = values[k];
+    const T v = values[k];
     const int8_t o = owner[k];
     const i64 at = slot[k];
     if (o == 0) vdia[at] = v;
     else if (o == 1) vbr[at] = v;
     else csr[at] = v;
-    aval[k] = v;
+    if (aval) aval[k] = v;
   }
 }
 
@@ -156,6 +158,7 @@ sable::i64 sable_plan_s::device_bytes() const {
        seg_ndiags.bytes() + seg_idiag_ptr.bytes() + seg_val_ptr.bytes();
   b += blk.bytes() + blk_val_ptr.bytes() + vbr_val.bytes() + vbr_mma.bytes() + blk_mma_ptr.bytes();
   b += csr_ptr.bytes() + csr_col.bytes() + csr_val.bytes();
+  b += vdia_val64.bytes() + vbr_val64.bytes() + csr_val64.bytes();
   b += a_ptr.bytes() + a_col.bytes() + a_val.bytes() + owner.bytes() + slot.bytes();
   for (int k = 0; k < 7; ++k) {
     const sable::Schedule* S = k < 3 ? &sched[k] : k < 6 ? &sched_plain[k - 3] : &sched_mm;
@@ -339,13 +342,54 @@ sable_status sable_update_values(sable_plan_t p, const float* values, void* stre
     if (!p || (!values && p->nnz)) SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     if (p->nnz) {
-      k_update_values<<<grid_for(p->nnz, 256), 256, 0, s>>>(values, p->nnz, p->owner.p, p->slot.p,
+      k_update_values<float><<<grid_for(p->nnz, 256), 256, 0, s>>>(values, p->nnz, p->owner.p, p->slot.p,
                                                             p->vdia_val.p, p->vbr_val.p,
                                                             p->csr_val.p, p->a_val.p);
       LAUNCH_CHECK();
     }
     if (p->vbr_cells && (p->flags & SABLE_F_SPLIT_BF16)) build_bf16_split(*p, s);
     refresh_far_values(*p, s);
+  });
+}
+
+sable_status sable_update_values_f64(sable_plan_t p, const double* values, void* stream) {
+  return guard([&] {
+    if (!p || (!values && p->nnz)) SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->has_f64) {  // first call: fp64 arrays, fill cells zero
+      p->vdia_val64.alloc(std::max<i64>(1, p->vdia_cells));
+      p->vbr_val64.alloc(std::max<i64>(1, p->vbr_cells));
+      p->csr_val64.alloc(std::max<i64>(1, p->csr_nnz));
+      HIPC(hipMemsetAsync(p->vdia_val64.p, 0, p->vdia_val64.bytes(), s));
+      HIPC(hipMemsetAsync(p->vbr_val64.p, 0, p->vbr_val64.bytes(), s));
+      HIPC(hipMemsetAsync(p->csr_val64.p, 0, p->csr_val64.bytes(), s));
+    }
+    if (p->nnz) {
+      k_update_values<double><<<grid_for(p->nnz, 256), 256, 0, s>>>(
+          values, p->nnz, p->owner.p, p->slot.p, p->vdia_val64.p, p->vbr_val64.p, p->csr_val64.p,
+          nullptr);
+      LAUNCH_CHECK();
+    }
+    p->has_f64 = true;
+  });
+}
+
+sable_status sable_spmv_f64(sable_plan_t p, const double* x, double* y, void* stream) {
+  return guard([&] {
+    if (!p || (!x && p->ncols) || (!y && p->nrows)) SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument");
+    if (!p->has_f64) SB_THROW(SABLE_ERR_INVALID_ARG, "no fp64 values: call sable_update_values_f64 first");
+    if (p->nrows == 0) return;
+    launch_spmv_f64(*p, x, y, (hipStream_t)stream);
+  });
+}
+
+sable_status sable_spmm_f64(sable_plan_t p, const double* X, double* Y, int32_t n, void* stream) {
+  return guard([&] {
+    if (!p || n < 1 || (!X && p->ncols) || (!Y && p->nrows))
+      SB_THROW(SABLE_ERR_INVALID_ARG, "NULL argument or n < 1");
+    if (!p->has_f64) SB_THROW(SABLE_ERR_INVALID_ARG, "no fp64 values: call sable_update_values_f64 first");
+    if (p->nrows == 0) return;
+    launch_spmm_f64(*p, X, Y, n, (hipStream_t)stream);
   });
 }
 

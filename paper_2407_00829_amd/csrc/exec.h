@@ -30,9 +30,29 @@ struct PlanView {
   const int32_t* tile_blk_ptr;
   const int32_t* tile_blk;
   const int32_t* tile_order;  // launch order of the streamed kernels (may be null)
+  // fp64 copies of the values (FP64 executor; null until set)
+  const double* vdia_val64;
+  const double* vbr_val64;
+  const double* csr_val64;
   // far-column split: when far_prod is set, csr_col holds negative codes -(1 + q) for entries
   // whose product far_prod[q] the gather pass has already computed
   const float* far_prod;
+};
+
+// Value arrays of the view for the executor's value type.
+template <class T>
+struct Vals;
+template <>
+struct Vals<float> {
+  __device__ static const float* vdia(const PlanView& P) { return P.vdia_val; }
+  __device__ static const float* vbr(const PlanView& P) { return P.vbr_val; }
+  __device__ static const float* csr(const PlanView& P) { return P.csr_val; }
+};
+template <>
+struct Vals<double> {
+  __device__ static const double* vdia(const PlanView& P) { return P.vdia_val64; }
+  __device__ static const double* vbr(const PlanView& P) { return P.vbr_val64; }
+  __device__ static const double* csr(const PlanView& P) { return P.csr_val64; }
 };
 
 // far = true: the view with the far-column split, if the plan has one and it is enabled.
@@ -143,44 +163,50 @@ __device__ __forceinline__ T ld(const T* p) {
 // csr_issue loads columns, values and the gathered operands; csr_finish forms the products
 // later, so other loads can be issued while the gathers are in flight. Indices past e_end
 // load entry e_end - 1 again and contribute 0, so every load is unconditional.
-template <int U>
+template <class T, int U>
 struct CsrFlight {
   int j[U];
-  float a[U], v[U];
+  T a[U], v[U];
 };
 
-template <bool NT, int U>
+template <class T, bool NT, int U>
 __device__ __forceinline__ void csr_issue(const PlanView& P, int e0, int e_end,
-                                          const float* __restrict__ x, CsrFlight<U>& f) {
+                                          const T* __restrict__ x, CsrFlight<T, U>& f) {
+  const T* val = Vals<T>::csr(P);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int k = min(e0 + (int)threadIdx.x + kSpmvThreads * u, e_end - 1);
     f.j[u] = ld<NT>(P.csr_col + k);
-    f.a[u] = ld<NT>(P.csr_val + k);
+    f.a[u] = ld<NT>(val + k);
   }
-  const float* fp = P.far_prod ? P.far_prod : x;
+  if constexpr (sizeof(T) == 4) {  // far-column products exist for fp32 only
+    const float* fp = P.far_prod ? P.far_prod : x;
 #pragma unroll
-  for (int u = 0; u < U; ++u) f.v[u] = *(f.j[u] >= 0 ? x + f.j[u] : fp + (-1 - f.j[u]));
+    for (int u = 0; u < U; ++u) f.v[u] = *(f.j[u] >= 0 ? x + f.j[u] : fp + (-1 - f.j[u]));
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) f.v[u] = x[f.j[u]];
+  }
 }
 
-template <int U>
-__device__ __forceinline__ void csr_finish(const CsrFlight<U>& f, int e0, int e_end, float (&pv)[U]) {
+template <class T, int U>
+__device__ __forceinline__ void csr_finish(const CsrFlight<T, U>& f, int e0, int e_end, T (&pv)[U]) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const float pr = f.j[u] >= 0 ? f.a[u] * f.v[u] : f.v[u];
-    pv[u] = e0 + (int)threadIdx.x + kSpmvThreads * u < e_end ? pr : 0.f;
+    const T pr = f.j[u] >= 0 ? f.a[u] * f.v[u] : f.v[u];
+    pv[u] = e0 + (int)threadIdx.x + kSpmvThreads * u < e_end ? pr : T(0);
   }
 }
 
-template <int RPT, bool NT = false>
+template <int RPT, bool NT = false, class T = float>
 __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
-                                                 const float* __restrict__ x,
-                                                 float* __restrict__ y, float* __restrict__ lds) {
+                                                 const T* __restrict__ x,
+                                                 T* __restrict__ y, float* __restrict__ lds) {
   constexpr int RT = kSpmvThreads * RPT;
   constexpr int U = CsrPass<RPT>::U;
   constexpr int kPass = U * kSpmvThreads;
-  float* prod = lds;                 // kPass products
-  float* part = lds + kCsrChunk;     // RT block partials
+  T* prod = reinterpret_cast<T*>(lds);  // kPass products (lds holds kCsrChunk + RT values of T)
+  T* part = prod + kCsrChunk;           // RT block partials
   const int r0 = tile * RT;
   const int t = threadIdx.x;
   const int rend = min(r0 + RT, P.nrows);
@@ -205,16 +231,16 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
     svp = P.seg_val_ptr[slo];
     sip = P.seg_idiag_ptr[slo];
   }
-  CsrFlight<U> fl;
-  if (e_begin < e_end) csr_issue<NT, U>(P, e_begin, e_end, x, fl);
+  CsrFlight<T, U> fl;
+  if (e_begin < e_end) csr_issue<T, NT, U>(P, e_begin, e_end, x, fl);
 
-  float acc[RPT];
+  T acc[RPT];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) acc[q] = 0.f;
+  for (int q = 0; q < RPT; ++q) acc[q] = 0;
   // 1. band segments
   for (int s = slo; s < shi; ++s) {
     const int32_t* od = P.idiag + sip;
-    const float* vb = P.vdia_val + svp;
+    const T* vb = Vals<T>::vdia(P) + svp;
     const int crs = rs, cnr = nr, cnd = nd;
     if (s + 1 < shi) {  // next descriptor
       rs = P.seg_row_start[s + 1];
@@ -227,7 +253,7 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
     for (int q = 0; q < RPT; ++q) {
       const int r = r0 + t + kSpmvThreads * q;
       if (r < crs || r >= crs + cnr || r >= rend) continue;
-      const float* v = vb + (r - crs);
+      const T* v = vb + (r - crs);
       // groups of four diagonals with predicated loads (a ribbon of 3 is one group)
       for (int d = 0; d < cnd; d += 4) {
         int c[4];
@@ -238,11 +264,11 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
           c[u] = d + u < cnd ? r + o : -1;
           ok[u] = (unsigned)c[u] < (unsigned)P.ncols;
         }
-        float vv[4], xv[4];
+        T vv[4], xv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          vv[u] = ok[u] ? ld<NT>(v + (i64)(d + u) * cnr) : 0.f;
-          xv[u] = ok[u] ? x[c[u]] : 0.f;
+          vv[u] = ok[u] ? ld<NT>(v + (i64)(d + u) * cnr) : T(0);
+          xv[u] = ok[u] ? x[c[u]] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -261,18 +287,18 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
     if (nrb <= 0) continue;
     const int S = nrb >= kSpmvThreads ? 1 : kSpmvThreads / nrb;
     const int cw = (w + S - 1) / S;
-    const float* vb = P.vbr_val + P.blk_val_ptr[b];
+    const T* vb = Vals<T>::vbr(P) + P.blk_val_ptr[b];
     __syncthreads();
     for (int i = t; i < nrb * S; i += kSpmvThreads) {
       const int rl = i % nrb, sl = i / nrb;
       const int row = lo + rl;
       const int cb = c0 + sl * cw, ce = min(c1, cb + cw);
-      const float* v = vb + (row - br0);
-      float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f;
+      const T* v = vb + (row - br0);
+      T p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p5 = 0, p6 = 0, p7 = 0;
       int c = cb;
       for (; c + 8 <= ce; c += 8) {
-        const float* vc = v + (i64)(c - c0) * h;
-        const float a0 = ld<NT>(vc), a1 = ld<NT>(vc + h), a2 = ld<NT>(vc + 2 * (i64)h),
+        const T* vc = v + (i64)(c - c0) * h;
+        const T a0 = ld<NT>(vc), a1 = ld<NT>(vc + h), a2 = ld<NT>(vc + 2 * (i64)h),
                     a3 = ld<NT>(vc + 3 * (i64)h), a4 = ld<NT>(vc + 4 * (i64)h),
                     a5 = ld<NT>(vc + 5 * (i64)h), a6 = ld<NT>(vc + 6 * (i64)h),
                     a7 = ld<NT>(vc + 7 * (i64)h);
@@ -297,19 +323,19 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
     for (int q = 0; q < RPT; ++q) {
       const int r = r0 + t + kSpmvThreads * q;
       if (r < lo || r >= hi) continue;
-      float sacc = 0.f;
+      T sacc = 0;
       for (int sl = 0; sl < S; ++sl) sacc += part[sl * nrb + (r - lo)];
       acc[q] += sacc;
     }
   }
   // 3. CSR: the first pass is already in registers
-  float cs[RPT];
+  T cs[RPT];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) cs[q] = 0.f;
-  float pv[U];
+  for (int q = 0; q < RPT; ++q) cs[q] = 0;
+  T pv[U];
   for (int e0 = e_begin; e0 < e_end; e0 += kPass) {
-    if (e0 != e_begin) csr_issue<NT, U>(P, e0, e_end, x, fl);
-    csr_finish<U>(fl, e0, e_end, pv);
+    if (e0 != e_begin) csr_issue<T, NT, U>(P, e0, e_end, x, fl);
+    csr_finish<T, U>(fl, e0, e_end, pv);
     const int n = min(kPass, e_end - e0);
     __syncthreads();  // previous pass's row sums are done with prod
 #pragma unroll

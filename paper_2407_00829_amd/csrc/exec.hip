@@ -20,6 +20,9 @@ PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool fa
   v.tile_blk_ptr = S.tile_blk_ptr.p;
   v.tile_blk = S.tile_blk.p;
   v.tile_order = S.order.p;
+  v.vdia_val64 = P.vdia_val64.p;
+  v.vbr_val64 = P.vbr_val64.p;
+  v.csr_val64 = P.csr_val64.p;
   if (plain) {
     v.csr_ptr = P.a_ptr.p;
     v.csr_col = P.a_col.p;
@@ -260,6 +263,28 @@ __global__ __launch_bounds__(kMmThreads, 4) void k_spmm_tile(PlanView P, const f
   spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, use_mfma != 0);
 }
 
+// FP64 executor: the same streamed SpMV tile body and SpMM tile (blocks on the VALU) over the
+// plan's fp64 value copies.
+template <int RPT>
+__global__ __launch_bounds__(256) void k_spmv_stream_f64(PlanView P, const double* __restrict__ x,
+                                                        double* __restrict__ y) {
+  __shared__ double lds[kCsrChunk + kSpmvThreads * RPT];
+  int tile = xcd_tile(blockIdx.x, P.ntiles);
+  if (tile >= P.ntiles) return;
+  if (P.tile_order) tile = P.tile_order[tile];
+  spmv_tile_stream<RPT, false, double>(P, tile, x, y, reinterpret_cast<float*>(lds));
+}
+
+__global__ __launch_bounds__(kMmThreads) void k_spmm_tile_f64(PlanView P, const double* __restrict__ X,
+                                                             double* __restrict__ Y, int n) {
+  __shared__ double ys[kMmRows * kMmCols + kMmBlkStage * kBlkDesc / 2];
+  const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
+  int t = xcd_tile(blockIdx.x, ntile);
+  if (t >= ntile) return;
+  if (P.tile_order) t = P.tile_order[t];
+  spmm_tile<double>(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, reinterpret_cast<float*>(ys), false);
+}
+
 // Fused SpMM (VALU): one wave per row, lanes across 64-column chunks of X / Y.
 __global__ __launch_bounds__(256) void k_spmm_fused_valu(PlanView P, const float* __restrict__ X,
                                                         float* __restrict__ Y, int n) {
@@ -489,6 +514,28 @@ void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStre
     const int mfma = (mode == 0 && P.vbr_mma.p != nullptr && P.nblk > 0) ? 1 : 0;
     k_spmm_tile<<<grid, kMmThreads, 0, s>>>(v, X, Y, n, mfma);
   }
+  LAUNCH_CHECK();
+}
+
+void launch_spmv_f64(const sable_plan_s& P, const double* x, double* y, hipStream_t s) {
+  // the streamed variant's tile size (rows per thread) if one is selected, else 1
+  const int var = P.prm.spmv_variant;
+  const int k = var <= 2 ? var : var >= 8 ? var - 8 : 0;
+  const PlanView v = make_view(P, P.sched[k], false);
+  const unsigned nb = (unsigned)(((v.ntiles + 7) / 8) * 8);
+  switch (k) {
+    case 0: k_spmv_stream_f64<1><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+    case 1: k_spmv_stream_f64<2><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+    default: k_spmv_stream_f64<4><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;
+  }
+  LAUNCH_CHECK();
+}
+
+void launch_spmm_f64(const sable_plan_s& P, const double* X, double* Y, int n, hipStream_t s) {
+  const PlanView v = make_view(P, P.sched_mm, false);
+  const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
+  dim3 grid((unsigned)(((ntile + 7) / 8) * 8), (unsigned)((n + kMmCols - 1) / kMmCols));
+  k_spmm_tile_f64<<<grid, kMmThreads, 0, s>>>(v, X, Y, n);
   LAUNCH_CHECK();
 }
 

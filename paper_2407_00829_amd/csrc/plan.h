@@ -100,6 +100,10 @@ struct sable_plan_s {
   sable::i64 csr_nnz = 0;
   sable::DBuf<int32_t> csr_ptr, csr_col;
   sable::DBuf<float> csr_val;
+  // fp64 copies of the format values for the FP64 executor (empty until
+  // sable_update_values_f64); same layouts as vdia_val / vbr_val / csr_val
+  sable::DBuf<double> vdia_val64, vbr_val64, csr_val64;
+  bool has_f64 = false;
   // Whole input as CSR (plain baseline) and owner/slot map of every input entry
   sable::DBuf<int32_t> a_ptr, a_col;
   sable::DBuf<float> a_val;
@@ -140,5 +144,7 @@ void refresh_far_values(sable_plan_s& P, hipStream_t s);
 void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s);
+void launch_spmv_f64(const sable_plan_s& P, const double* x, double* y, hipStream_t s);
+void launch_spmm_f64(const sable_plan_s& P, const double* X, double* Y, int n, hipStream_t s);
 
 }  // namespace sable

@@ -152,12 +152,51 @@ __device__ __forceinline__ void mfma_small_batch(const PlanView& P, const int* s
   }
 }
 
+// Blocks on the VALU in the tile's value type: lanes across columns, one row per lane group;
+// block partials are added to the band partials in ys (the tile of Y in LDS).
+template <class T>
+__device__ __forceinline__ void spmm_blocks_valu(const PlanView& P, int* sb, int blo, int bhi, int r0,
+                                                 int rend, int cb, int n, const T* __restrict__ X,
+                                                 T* __restrict__ ys, int wave, int rpw, int sub,
+                                                 int cA, int cB, bool okA, bool okB) {
+    for (int q0 = blo; q0 < bhi; q0 += kMmBlkStage) {
+     const int nq = min(kMmBlkStage, bhi - q0);
+     stage_blocks(P, q0, nq, sb);
+     for (int j = 0; j < nq; ++j) {
+      const int* dsc = sb + kBlkDesc * j;
+      const int br0 = dsc[0], br1 = dsc[1];
+      const int lo = max(br0, r0), hi = min(br1, rend);
+      if (lo >= hi) continue;
+      const int c0 = dsc[2], c1 = dsc[3];
+      const int h = br1 - br0, w = c1 - c0;
+      const i64 vp = (i64)(((uint64_t)(uint32_t)dsc[5] << 32) | (uint32_t)dsc[4]);
+      for (int rl = wave * rpw + sub; rl < kMmRows; rl += 4 * rpw) {
+        const int r = r0 + rl;
+        if (r < lo || r >= hi) continue;
+        const T* v = Vals<T>::vbr(P) + vp + (r - br0);
+        T a0 = 0, a1 = 0;
+        for (int k = 0; k < w; ++k) {
+          const T a = v[(i64)k * h];
+          const T* xr = X + (i64)(c0 + k) * n + cb;
+          if (okA) a0 += a * xr[cA];
+          if (okB) a1 += a * xr[cB];
+        }
+        if (okA) ys[rl * kMmCols + cA] += a0;
+        if (okB) ys[rl * kMmCols + cB] += a1;
+      }
+     }
+    }
+    __syncthreads();
+}
+
 // Rows [r0, r0+kMmRows) x columns [cb, cb+nc) of Y. lds = kMmRows x kMmCols floats for the
 // tile of Y, then kMmBlkStage block descriptors (r0, r1, c0, c1, value offset). The view's
 // schedule has tiles of kMmRows rows, so tile lists hold exactly the overlapping blocks.
+template <class T = float>
 __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int n,
-                                          const float* __restrict__ X, float* __restrict__ Y,
-                                          float* __restrict__ ys, bool use_mfma) {
+                                          const T* __restrict__ X, T* __restrict__ Y,
+                                          float* __restrict__ lds, bool use_mfma) {
+  T* ys = reinterpret_cast<T*>(lds);                          // kMmRows x kMmCols values of T
   int* sb = reinterpret_cast<int*>(ys + kMmRows * kMmCols);  // [kMmBlkStage][kBlkDesc]
   const int nc = min(kMmCols, n - cb);
   const int rend = min(r0 + kMmRows, P.nrows);
@@ -174,19 +213,19 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
   // 1. bands
   for (int rl = wave * rpw + sub; rl < kMmRows; rl += 4 * rpw) {
     const int r = r0 + rl;
-    float a0 = 0.f, a1 = 0.f;
+    T a0 = 0, a1 = 0;
     if (r < rend) {
       for (int s = P.tile_seg_lo[tile]; s < P.tile_seg_hi[tile]; ++s) {
         const int rs = P.seg_row_start[s], nr = P.seg_nrows[s];
         if (r < rs || r >= rs + nr) continue;
         const int nd = P.seg_ndiags[s];
         const int32_t* od = P.idiag + P.seg_idiag_ptr[s];
-        const float* v = P.vdia_val + P.seg_val_ptr[s] + (r - rs);
+        const T* v = Vals<T>::vdia(P) + P.seg_val_ptr[s] + (r - rs);
         for (int d = 0; d < nd; ++d) {
           const int c = r + od[d];
           if ((unsigned)c >= (unsigned)P.ncols) continue;
-          const float a = v[(i64)d * nr];
-          const float* xr = X + (i64)c * n + cb;
+          const T a = v[(i64)d * nr];
+          const T* xr = X + (i64)c * n + cb;
           if (okA) a0 += a * xr[cA];
           if (okB) a1 += a * xr[cB];
         }
@@ -199,7 +238,8 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
 
   // 2. blocks
   const int blo = P.tile_blk_ptr[tile], bhi = P.tile_blk_ptr[tile + 1];
-  if (use_mfma) {
+  if constexpr (sizeof(T) == 4) {  // matrix cores for the fp32 executor only
+   if (use_mfma) {
     // Wave w owns the 16-column chunks w and w+4 of this column block and all four 16-row
     // slices of the tile; products accumulate in registers over the tile's blocks in block
     // order, then are added to the band partial in LDS.
@@ -294,42 +334,18 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
       }
       __syncthreads();
     }
+   } else {
+    spmm_blocks_valu<T>(P, sb, blo, bhi, r0, rend, cb, n, X, ys, wave, rpw, sub, cA, cB, okA, okB);
+   }
   } else {
-    for (int q0 = blo; q0 < bhi; q0 += kMmBlkStage) {
-     const int nq = min(kMmBlkStage, bhi - q0);
-     stage_blocks(P, q0, nq, sb);
-     for (int j = 0; j < nq; ++j) {
-      const int* dsc = sb + kBlkDesc * j;
-      const int br0 = dsc[0], br1 = dsc[1];
-      const int lo = max(br0, r0), hi = min(br1, rend);
-      if (lo >= hi) continue;
-      const int c0 = dsc[2], c1 = dsc[3];
-      const int h = br1 - br0, w = c1 - c0;
-      const i64 vp = (i64)(((uint64_t)(uint32_t)dsc[5] << 32) | (uint32_t)dsc[4]);
-      for (int rl = wave * rpw + sub; rl < kMmRows; rl += 4 * rpw) {
-        const int r = r0 + rl;
-        if (r < lo || r >= hi) continue;
-        const float* v = P.vbr_val + vp + (r - br0);
-        float a0 = 0.f, a1 = 0.f;
-        for (int k = 0; k < w; ++k) {
-          const float a = v[(i64)k * h];
-          const float* xr = X + (i64)(c0 + k) * n + cb;
-          if (okA) a0 += a * xr[cA];
-          if (okB) a1 += a * xr[cB];
-        }
-        if (okA) ys[rl * kMmCols + cA] += a0;
-        if (okB) ys[rl * kMmCols + cB] += a1;
-      }
-     }
-    }
-    __syncthreads();
+    spmm_blocks_valu<T>(P, sb, blo, bhi, r0, rend, cb, n, X, ys, wave, rpw, sub, cA, cB, okA, okB);
   }
 
   // 3. CSR, then store
   for (int rl = wave * rpw + sub; rl < kMmRows; rl += 4 * rpw) {
     const int r = r0 + rl;
     if (r >= rend) continue;
-    float a0 = 0.f, a1 = 0.f;
+    T a0 = 0, a1 = 0;
     const int ke = P.csr_ptr[r + 1];
     int k = P.csr_ptr[r];
     // eight X rows in flight per lane: indices and values first, then every X load
@@ -337,31 +353,31 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
     const int cAc = min(cA, nc - 1), cBc = min(cB, nc - 1);
     for (; k + 8 <= ke; k += 8) {
       int cc[8];
-      float va[8], xa[8], xb[8];
+      T va[8], xa[8], xb[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         cc[u] = P.csr_col[k + u];
-        va[u] = P.csr_val[k + u];
+        va[u] = Vals<T>::csr(P)[k + u];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const float* xr = X + (i64)cc[u] * n + cb;
+        const T* xr = X + (i64)cc[u] * n + cb;
         xa[u] = xr[cAc];
         xb[u] = xr[cBc];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        a0 += va[u] * (okA ? xa[u] : 0.f);
-        a1 += va[u] * (okB ? xb[u] : 0.f);
+        a0 += va[u] * (okA ? xa[u] : T(0));
+        a1 += va[u] * (okB ? xb[u] : T(0));
       }
     }
     for (; k < ke; ++k) {
-      const float v0 = P.csr_val[k];
-      const float* x0 = X + (i64)P.csr_col[k] * n + cb;
+      const T v0 = Vals<T>::csr(P)[k];
+      const T* x0 = X + (i64)P.csr_col[k] * n + cb;
       if (okA) a0 += v0 * x0[cA];
       if (okB) a1 += v0 * x0[cB];
     }
-    float* yr = Y + (i64)r * n + cb;
+    T* yr = Y + (i64)r * n + cb;
     if (okA) yr[cA] = ys[rl * kMmCols + cA] + a0;
     if (okB) yr[cB] = ys[rl * kMmCols + cB] + a1;
   }

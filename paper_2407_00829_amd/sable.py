@@ -31,6 +31,7 @@ EXPORTED = [
     "sable_update_values", "sable_autotune", "sable_plan_set_variant", "sable_features", "sable_class_plan",
     "sable_mlp_forward", "sable_mlp_train_step", "sable_plan_exhaustive", "sable_plan_auto", "sable_batch_create", "sable_batch_run",
     "sable_batch_latencies", "sable_batch_destroy", "sable_last_error",
+    "sable_update_values_f64", "sable_spmv_f64", "sable_spmm_f64",
 ]
 
 
@@ -120,6 +121,9 @@ def lib():
         "sable_batch_run": [P, P],
         "sable_batch_latencies": [P, P, P],
         "sable_batch_destroy": [P],
+        "sable_update_values_f64": [P, P, P],
+        "sable_spmv_f64": [P, P, P, P],
+        "sable_spmm_f64": [P, P, P, i32, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -262,6 +266,18 @@ def sable_spmm(p: Plan, X, Y, n: int, stream=None) -> None:
 
 def sable_update_values(p: Plan, values, stream=None) -> None:
     _check("sable_update_values", lib().sable_update_values(p.h, _ptr(values), _stream(stream)))
+
+
+def sable_update_values_f64(p: Plan, values, stream=None) -> None:
+    _check("sable_update_values_f64", lib().sable_update_values_f64(p.h, _ptr(values), _stream(stream)))
+
+
+def sable_spmv_f64(p: Plan, x, y, stream=None) -> None:
+    _check("sable_spmv_f64", lib().sable_spmv_f64(p.h, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def sable_spmm_f64(p: Plan, X, Y, n: int, stream=None) -> None:
+    _check("sable_spmm_f64", lib().sable_spmm_f64(p.h, _ptr(X), _ptr(Y), int(n), _stream(stream)))
 
 
 def sable_error_norm_f64(y, yref, stream=None) -> float:
