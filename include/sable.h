@@ -225,7 +225,9 @@ sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, const float* 
 /* Select a fused-kernel variant explicitly (the set sable_autotune chooses from).
  * op 0 = hybrid SpMV: 0..2 streamed tiles of 256/512/1024 rows, 3..7 row-per-lane with
  *        1/2/4/8/16 lanes per CSR row, 8..10 = 0..2 with non-temporal matrix loads;
- * op 1 = SpMM: 0 tiled with matrix-core blocks, 1 tiled fp32, 2 one wave per row;
+ * op 1 = SpMM: 0 tiled with matrix-core blocks (for n <= 32 the four waves split the tile's
+ *        row slices, otherwise its column chunks), 1 tiled fp32, 2 one wave per row, 3 tiled
+ *        with matrix-core blocks and the column-chunk split at every n;
  * op 2 = plain CSR baseline: 0..2 streamed, 3..9 with 1..64 lanes per row, 10..12 = 0..2
  *        with non-temporal matrix loads;
  * op 3 = far-column split of the streamed SpMV variants: 0 off, 1 on (when the plan has one).

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256, 3) void k_batch(const PlanView* __restrict__ v
       int rt = local % I.units_per_col;
       const int cc = local / I.units_per_col;
       if (P.tile_order) rt = P.tile_order[rt];
-      spmm_tile(P, rt * kMmRows, cc * kMmCols, I.n, I.x, I.y, lds, I.mfma != 0);
+      spmm_tile(P, rt * kMmRows, cc * kMmCols, I.n, I.x, I.y, lds, I.mfma);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -146,7 +146,7 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
         hv[i] = make_view(P, P.sched_mm, false);
         d.units_per_col = (P.nrows + kMmRows - 1) / kMmRows;
         d.col_chunks = (it.n + kMmCols - 1) / kMmCols;
-        d.mfma = (P.prm.spmm_mode == 0 && P.vbr_mma.p && P.nblk > 0) ? 1 : 0;
+        d.mfma = spmm_mfma_mode(P);
         units = (i64)d.units_per_col * d.col_chunks;
       }
       hi[i] = d;

@@ -254,13 +254,13 @@ __global__ __launch_bounds__(256) void k_spmv_plain(const int32_t* __restrict__ 
 }
 
 __global__ __launch_bounds__(kMmThreads, 4) void k_spmm_tile(PlanView P, const float* __restrict__ X,
-                                                         float* __restrict__ Y, int n, int use_mfma) {
+                                                         float* __restrict__ Y, int n, int mfma) {
   __shared__ float ys[kMmRows * kMmCols + kMmBlkStage * kBlkDesc];
   const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
   int t = xcd_tile(blockIdx.x, ntile);
   if (t >= ntile) return;
   if (P.tile_order) t = P.tile_order[t];
-  spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, use_mfma != 0);
+  spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, mfma);
 }
 
 // FP64 executor: the same streamed SpMV tile body and SpMM tile (blocks on the VALU) over the
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kMmThreads) void k_spmm_tile_f64(PlanView P, const 
   int t = xcd_tile(blockIdx.x, ntile);
   if (t >= ntile) return;
   if (P.tile_order) t = P.tile_order[t];
-  spmm_tile<double>(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, reinterpret_cast<float*>(ys), false);
+  spmm_tile<double>(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, reinterpret_cast<float*>(ys), 0);
 }
 
 // Fused SpMM (VALU): one wave per row, lanes across 64-column chunks of X / Y.
@@ -502,6 +502,11 @@ void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStrea
   LAUNCH_CHECK();
 }
 
+int spmm_mfma_mode(const sable_plan_s& P) {
+  if (!P.vbr_mma.p || P.nblk == 0) return 0;
+  return P.prm.spmm_mode == 0 ? 1 : P.prm.spmm_mode == 3 ? 2 : 0;
+}
+
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s) {
   const PlanView v = make_view(P, P.prm.spmm_mode == 2 ? P.sched[0] : P.sched_mm, false);
   const int mode = P.prm.spmm_mode;
@@ -511,7 +516,7 @@ void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStre
   } else {
     const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
     dim3 grid((unsigned)(((ntile + 7) / 8) * 8), (unsigned)((n + kMmCols - 1) / kMmCols));
-    const int mfma = (mode == 0 && P.vbr_mma.p != nullptr && P.nblk > 0) ? 1 : 0;
+    const int mfma = spmm_mfma_mode(P);
     k_spmm_tile<<<grid, kMmThreads, 0, s>>>(v, X, Y, n, mfma);
   }
   LAUNCH_CHECK();

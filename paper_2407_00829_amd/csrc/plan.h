@@ -31,7 +31,8 @@ struct BlkRec {  // block rectangle rows [r0, r1), columns [c0, c1)
 struct ExecParams {
   int spmv_variant = 1;
   int plain_variant = 1;
-  int spmm_mode = 0;  // fused SpMM variant
+  int spmm_mode = 0;  // fused SpMM variant: 0 tiled, matrix cores (automatic work split),
+                      // 1 tiled fp32 VALU, 2 wave per row, 3 tiled, matrix cores (chunk split)
   int far_split = 1;  // streamed SpMV: gather far-column CSR entries in a separate pass
 };
 
@@ -144,6 +145,8 @@ void refresh_far_values(sable_plan_s& P, hipStream_t s);
 void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s);
+// Matrix-core mode of the tiled SpMM for the plan's variant (0 none, 1 auto split, 2 chunks).
+int spmm_mfma_mode(const sable_plan_s& P);
 void launch_spmv_f64(const sable_plan_s& P, const double* x, double* y, hipStream_t s);
 void launch_spmm_f64(const sable_plan_s& P, const double* X, double* Y, int n, hipStream_t s);
 

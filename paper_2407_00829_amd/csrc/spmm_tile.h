@@ -76,10 +76,19 @@ __device__ __forceinline__ void stage_blocks(const PlanView& P, int q0, int nq, 
   __syncthreads();
 }
 
+// Which part of the tile's products a wave computes on the matrix cores: 16-column chunks
+// c0 and c0 + cstep of the column block, for the 16-row slices whose bit is set in smask.
+// Wide column blocks (more than 32 columns) split the chunks over the waves (c0 = wave,
+// cstep = 4, every slice); narrow ones (n <= 32) split the slices (c0 = 0, cstep = 1, slice
+// wave only), so all four waves have work.
+struct MmPart {
+  int c0, cstep, smask;
+};
+
 // Three split-bf16 products of one 16x16x16 step into acc[0..1] (the wave's two column
 // chunks): a = packed hi|lo words of this lane's four k values, b = X fragments.
 __device__ __forceinline__ void mfma3(floatx4_t (&acc)[2], const uint4& aw, const bf16x4_t (&bh)[2],
-                                      const bf16x4_t (&bl)[2], int wave, int nc) {
+                                      const bf16x4_t (&bl)[2], const MmPart& mp, int nc) {
   bf16x4_t ah, al;
   ah[0] = (short)(aw.x & 0xffffu); al[0] = (short)(aw.x >> 16);
   ah[1] = (short)(aw.y & 0xffffu); al[1] = (short)(aw.y >> 16);
@@ -87,7 +96,7 @@ __device__ __forceinline__ void mfma3(floatx4_t (&acc)[2], const uint4& aw, cons
   ah[3] = (short)(aw.w & 0xffffu); al[3] = (short)(aw.w >> 16);
 #pragma unroll
   for (int ci = 0; ci < 2; ++ci) {
-    if ((wave + 4 * ci) * 16 >= nc) continue;
+    if ((mp.c0 + mp.cstep * ci) * 16 >= nc) continue;
     acc[ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[ci], acc[ci], 0, 0, 0);
     acc[ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[ci], acc[ci], 0, 0, 0);
     acc[ci] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[ci], acc[ci], 0, 0, 0);
@@ -101,8 +110,8 @@ __device__ __forceinline__ void mfma3(floatx4_t (&acc)[2], const uint4& aw, cons
 __device__ __forceinline__ void mfma_small_batch(const PlanView& P, const int* sb, const int (&ib)[kMmBatch],
                                                  const int (&ik)[kMmBatch],
                                                  int cnt, int r0, int rend, int cb, int n, int nc,
-                                                 const float* __restrict__ X, int wave, int m, int kg,
-                                                 floatx4_t (&acc)[4][2]) {
+                                                 const float* __restrict__ X, const MmPart& part,
+                                                 int m, int kg, floatx4_t (&acc)[4][2]) {
   float xr[kMmBatch][2][4];
   uint4 aw[kMmBatch][2];
   int ma[kMmBatch], nsl[kMmBatch];
@@ -124,7 +133,7 @@ __device__ __forceinline__ void mfma_small_batch(const PlanView& P, const int* s
       const float* xrow = X + (i64)(c0 + min(k, w - 1)) * n + cb;
 #pragma unroll
       for (int ci = 0; ci < 2; ++ci) {
-        const int col = (wave + 4 * ci) * 16 + m;
+        const int col = (part.c0 + part.cstep * ci) * 16 + m;
         xr[s][ci][i] = xrow[min(col, nc - 1)];
         if (!(sv && col < nc && k < w)) xr[s][ci][i] = 0.f;
       }
@@ -146,8 +155,8 @@ __device__ __forceinline__ void mfma_small_batch(const PlanView& P, const int* s
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {  // slices ascending; ma[s] is wave-uniform
       const int sl = mt - ma[s];
-      if (sl < 0 || sl >= nsl[s]) continue;
-      mfma3(acc[mt], sl == 0 ? aw[s][0] : aw[s][1], bh, bl, wave, nc);
+      if (sl < 0 || sl >= nsl[s] || !((part.smask >> mt) & 1)) continue;
+      mfma3(acc[mt], sl == 0 ? aw[s][0] : aw[s][1], bh, bl, part, nc);
     }
   }
 }
@@ -192,10 +201,12 @@ __device__ __forceinline__ void spmm_blocks_valu(const PlanView& P, int* sb, int
 // Rows [r0, r0+kMmRows) x columns [cb, cb+nc) of Y. lds = kMmRows x kMmCols floats for the
 // tile of Y, then kMmBlkStage block descriptors (r0, r1, c0, c1, value offset). The view's
 // schedule has tiles of kMmRows rows, so tile lists hold exactly the overlapping blocks.
+// mfma: 0 = blocks on the VALU, 1 = matrix cores with the automatic work split (slices over
+// the waves for n <= 32 columns, chunks otherwise), 2 = matrix cores, chunks over the waves.
 template <class T = float>
 __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int n,
                                           const T* __restrict__ X, T* __restrict__ Y,
-                                          float* __restrict__ lds, bool use_mfma) {
+                                          float* __restrict__ lds, int mfma) {
   T* ys = reinterpret_cast<T*>(lds);                          // kMmRows x kMmCols values of T
   int* sb = reinterpret_cast<int*>(ys + kMmRows * kMmCols);  // [kMmBlkStage][kBlkDesc]
   const int nc = min(kMmCols, n - cb);
@@ -239,16 +250,18 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
   // 2. blocks
   const int blo = P.tile_blk_ptr[tile], bhi = P.tile_blk_ptr[tile + 1];
   if constexpr (sizeof(T) == 4) {  // matrix cores for the fp32 executor only
-   if (use_mfma) {
-    // Wave w owns the 16-column chunks w and w+4 of this column block and all four 16-row
-    // slices of the tile; products accumulate in registers over the tile's blocks in block
-    // order, then are added to the band partial in LDS.
+   if (mfma) {
+    // Each wave owns part of the products (MmPart: two 16-column chunks and a set of 16-row
+    // slices); they accumulate in registers over the tile's blocks in block order, then are
+    // added to the band partial in LDS. Every output element sees the same operations in
+    // either split, so results do not depend on it.
     floatx4_t acc[4][2];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
       for (int ci = 0; ci < 2; ++ci) acc[mt][ci] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     const int m = lane & 15, kg = lane >> 4;  // MFMA operand coordinates of this lane
+    const MmPart part = (mfma == 1 && nc <= 32) ? MmPart{0, 1, 1 << wave} : MmPart{wave, 4, 0xF};
     for (int q0 = blo; q0 < bhi; q0 += kMmBlkStage) {
      const int nq = min(kMmBlkStage, bhi - q0);
      stage_blocks(P, q0, nq, sb);
@@ -272,7 +285,7 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
         if (kk0 >= d[3] - d[2]) { ++jj; kk0 = 0; }
       }
       if (cnt > 0) {
-        mfma_small_batch(P, sb, ib, ik, cnt, r0, rend, cb, n, nc, X, wave, m, kg, acc);
+        mfma_small_batch(P, sb, ib, ik, cnt, r0, rend, cb, n, nc, X, part, m, kg, acc);
         j = jj;
         kstart = kk0;
         continue;
@@ -294,7 +307,7 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
         float xr[2][4];
 #pragma unroll
         for (int ci = 0; ci < 2; ++ci) {
-          const int col = (wave + 4 * ci) * 16 + m;
+          const int col = (part.c0 + part.cstep * ci) * 16 + m;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int k = kk + i;
@@ -316,8 +329,8 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
           const int m0 = r0 + 16 * mt;
-          if (m0 >= hi || m0 + 16 <= lo) continue;
-          mfma3(acc[mt], aw[mt], bh, bl, wave, nc);
+          if (m0 >= hi || m0 + 16 <= lo || !((part.smask >> mt) & 1)) continue;
+          mfma3(acc[mt], aw[mt], bh, bl, part, nc);
         }
       }
      }
@@ -325,12 +338,14 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
     if (blo < bhi) {
 #pragma unroll
       for (int ci = 0; ci < 2; ++ci) {
-        const int col = (wave + 4 * ci) * 16 + m;
+        const int col = (part.c0 + part.cstep * ci) * 16 + m;
         if (col >= nc) continue;
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int mt = 0; mt < 4; ++mt) {
+          if (!((part.smask >> mt) & 1)) continue;
 #pragma unroll
           for (int i = 0; i < 4; ++i) ys[(16 * mt + 4 * kg + i) * kMmCols + col] += acc[mt][ci][i];
+        }
       }
       __syncthreads();
     }

@@ -74,8 +74,8 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
     P.prm.plain_variant = pick(tp);
   } else {
     // x / y hold X (ncols x n) and Y (nrows x n)
-    std::vector<float> t(3);
-    for (int m = 0; m <= 2; ++m) {
+    std::vector<float> t(4);
+    for (int m = 0; m <= 3; ++m) {
       P.prm.spmm_mode = m;
       t[m] = time_ms([&] { launch_spmm(P, x, y, n, s); }, s, 2);
     }
@@ -110,7 +110,7 @@ extern "C" sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32
     sable::set_error("NULL plan");
     return SABLE_ERR_INVALID_ARG;
   }
-  const int maxv = op == 0 ? 10 : op == 1 ? 2 : op == 2 ? 12 : op == 3 ? 1 : -1;
+  const int maxv = op == 0 ? 10 : op == 1 ? 3 : op == 2 ? 12 : op == 3 ? 1 : -1;
   if (variant < 0 || variant > maxv) {
     sable::set_error("variant %d out of range for op %d", variant, op);
     return SABLE_ERR_INVALID_ARG;

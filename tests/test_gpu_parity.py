@@ -224,7 +224,7 @@ def test_spmm_modes_and_widths(n):
     A, _ = synth.gen_c1(4, n=1536)
     th = oracle.Thresholds(amin_band=256, amin_block=256)
     p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
-    for mode in range(3):
+    for mode in range(4):
         sable.sable_plan_set_variant(p, 1, mode)
         check_spmm(p, A, n, seed=n)
 
