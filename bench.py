@@ -438,6 +438,41 @@ def run_batch(args, torch, sable, synth):
     }
 
 
+def run_spec(args, torch, sable, synth):
+    """Run-time specialization vs the generic fused kernels on small matrices: for each of
+    --count C5-style matrices (SpMV), the autotuned generic variant and the hipRTC-specialized
+    kernel, per-launch event time; geomean speedup and compile time."""
+    import concurrent.futures as cf
+    seeds = [args.seed * 100000 + i for i in range(args.count)]
+    with cf.ProcessPoolExecutor(8) as ex:
+        mats = list(ex.map(synth.gen_c5_matrix, seeds))
+    th = sable.Thresholds()
+    ratios, comp, skipped = [], [], 0
+    for i, (A, kind, op) in enumerate(mats):
+        p = sable.plan_host(A, [sable.SABLE_X_VDIA, sable.SABLE_X_VBR, sable.SABLE_X_CSR],
+                            sable.SABLE_VBR_TILED, th)
+        x = torch.from_numpy(synth.gen_dense_vector(i, A.ncols)).cuda()
+        y = torch.empty(A.nrows, device="cuda")
+        sable.sable_autotune(p, 0, 1, x, y)
+        _, t_gen = timed_steps(lambda: sable.sable_spmv(p, x, y), 50, 10, torch)
+        try:
+            sable.sable_plan_specialize(p)
+        except sable.SableError:
+            skipped += 1
+            continue
+        comp.append(sable.sable_plan_info(p)["spec_ms"])
+        sable.sable_plan_set_variant(p, 0, 11)
+        _, t_spec = timed_steps(lambda: sable.sable_spmv(p, x, y), 50, 10, torch)
+        ratios.append(t_gen / t_spec)
+        p.destroy()
+    r = np.array(ratios)
+    return {"workload": "spec", "matrices": len(r), "too_large": skipped,
+            "geomean_speedup_spec_vs_generic": float(np.exp(np.mean(np.log(r)))),
+            "spec_faster_fraction": float(np.mean(r > 1.0)),
+            "speedup_p10_p50_p90": [float(v) for v in np.percentile(r, [10, 50, 90])],
+            "compile_ms_median": float(np.median(comp))}
+
+
 def run_copy(args, torch):
     """Plain elementwise device copy (1 GiB read, 1 GiB written): the reference for scaling
     HBM byte counters."""
@@ -456,7 +491,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "batch", "copy"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "batch", "spec", "copy"])
     ap.add_argument("--count", type=int, default=256)
     ap.add_argument("--plan", default="hybrid", choices=["hybrid", "vbr"])
     ap.add_argument("--seed", type=int, default=0)
@@ -486,6 +521,8 @@ def main():
         out = run_spmm(args, torch, sable, synth)
     elif args.workload == "batch":
         out = run_batch(args, torch, sable, synth)
+    elif args.workload == "spec":
+        out = run_spec(args, torch, sable, synth)
     else:
         out = run_copy(args, torch)
     print(json.dumps(out), flush=True)

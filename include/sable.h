@@ -123,6 +123,7 @@ typedef struct {
   int32_t far_split;       /* 1 if the streamed SpMV variants gather far-column CSR entries
                               in a separate pass (see sable_spmv) */
   int64_t far_nnz;         /* CSR entries handled by that pass */
+  double spec_ms;          /* wall time of sable_plan_specialize (0 if not specialized) */
 } sable_plan_stats;
 
 /* Host buffers for sable_plan_export, sized from sable_plan_info:
@@ -224,7 +225,8 @@ sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, const float* 
 
 /* Select a fused-kernel variant explicitly (the set sable_autotune chooses from).
  * op 0 = hybrid SpMV: 0..2 streamed tiles of 256/512/1024 rows, 3..7 row-per-lane with
- *        1/2/4/8/16 lanes per CSR row, 8..10 = 0..2 with non-temporal matrix loads;
+ *        1/2/4/8/16 lanes per CSR row, 8..10 = 0..2 with non-temporal matrix loads,
+ *        11 = the run-time specialized kernel (after sable_plan_specialize);
  * op 1 = SpMM: 0 tiled with matrix-core blocks (for n <= 32 the four waves split the tile's
  *        row slices, otherwise its column chunks), 1 tiled fp32, 2 one wave per row, 3 tiled
  *        with matrix-core blocks and the column-chunk split at every n;
@@ -233,6 +235,19 @@ sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, const float* 
  * op 3 = far-column split of the streamed SpMV variants: 0 off, 1 on (when the plan has one).
  * Every variant computes the same product; each is bitwise reproducible on its own. */
 sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32_t variant);
+
+/* ---- Run-time specialization (Sec. 3.3 - 3.4 code generation, on the GPU) ------------
+ * Generate HIP source for this plan's SpMV with every band segment (rows, diagonal offsets,
+ * value offset) and every VBR block (rectangle, value offset) as literal constants, compile it
+ * with hipRTC for the current device and keep it in the plan as SpMV variant 11 (the
+ * autotuner then considers it). Work is one thread per row, one workgroup per 256-row tile,
+ * the tile's CSR entries streamed through LDS; per row (bands, diagonals ascending, then
+ * blocks in block order) + CSR in index order.
+ * Meant for small matrices: SABLE_ERR_TOO_LARGE if the plan has more than 4096 tiles,
+ * more than 16384 (tile, segment or block) pairs or a segment wider than 128 diagonals;
+ * SABLE_ERR_HIP with the compiler log in sable_last_error if compilation fails.
+ * Synchronous; a second call is a no-op. */
+sable_status sable_plan_specialize(sable_plan_t p, void* stream);
 
 /* ---- Learned planner (matrix features -> MLP -> extractor list and delta) ------------- */
 #define SABLE_NFEAT 140

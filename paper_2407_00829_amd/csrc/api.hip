@@ -278,6 +278,7 @@ sable_status sable_plan_info(sable_plan_t p, sable_plan_stats* o) {
     o->plain_variant = p->prm.plain_variant;
     o->far_split = (p->far.npanel && p->prm.far_split) ? 1 : 0;
     o->far_nnz = p->far.nfar;
+    o->spec_ms = p->spec_ms;
   });
 }
 

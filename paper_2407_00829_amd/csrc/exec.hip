@@ -456,6 +456,10 @@ SABLE_STREAM_LAUNCH(k_csr_stream)
 
 void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
   const int var = P.prm.spmv_variant;
+  if (var == 11) {
+    launch_spmv_spec(P, x, y, s);
+    return;
+  }
   if (var <= 2 || var >= 8) {
     const int k = var <= 2 ? var : var - 8;
     const PlanView v = make_view(P, P.sched[k], false, true);

@@ -118,7 +118,12 @@ struct sable_plan_s {
   sable::ExecParams prm;
   uint32_t flags = 0;
   double plan_ms = 0.0;
+  // run-time specialized SpMV (hipRTC module and kernel; null until sable_plan_specialize)
+  void* spec_module = nullptr;
+  void* spec_func = nullptr;
+  double spec_ms = 0.0;
   sable::i64 device_bytes() const;
+  ~sable_plan_s();
 };
 
 namespace sable {
@@ -148,6 +153,7 @@ void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStre
 // Matrix-core mode of the tiled SpMM for the plan's variant (0 none, 1 auto split, 2 chunks).
 int spmm_mfma_mode(const sable_plan_s& P);
 void launch_spmv_f64(const sable_plan_s& P, const double* x, double* y, hipStream_t s);
+void launch_spmv_spec(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmm_f64(const sable_plan_s& P, const double* X, double* Y, int n, hipStream_t s);
 
 }  // namespace sable

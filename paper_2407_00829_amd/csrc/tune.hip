@@ -55,6 +55,11 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
       t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
       cand.push_back({v, 0});
     }
+    if (P.spec_func) {  // the run-time specialized kernel, ranked after the generic ones
+      P.prm.spmv_variant = 11;
+      t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
+      cand.push_back({11, 0});
+    }
     if (P.far.npanel) {
       P.prm.far_split = 1;
       for (int v : {0, 1, 2, 8, 9, 10}) {
@@ -110,9 +115,13 @@ extern "C" sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32
     sable::set_error("NULL plan");
     return SABLE_ERR_INVALID_ARG;
   }
-  const int maxv = op == 0 ? 10 : op == 1 ? 3 : op == 2 ? 12 : op == 3 ? 1 : -1;
+  const int maxv = op == 0 ? 11 : op == 1 ? 3 : op == 2 ? 12 : op == 3 ? 1 : -1;
   if (variant < 0 || variant > maxv) {
     sable::set_error("variant %d out of range for op %d", variant, op);
+    return SABLE_ERR_INVALID_ARG;
+  }
+  if (op == 0 && variant == 11 && !p->spec_func) {
+    sable::set_error("variant 11 needs sable_plan_specialize first");
     return SABLE_ERR_INVALID_ARG;
   }
   if (op == 0) p->prm.spmv_variant = variant;

@@ -31,7 +31,7 @@ EXPORTED = [
     "sable_update_values", "sable_autotune", "sable_plan_set_variant", "sable_features", "sable_class_plan",
     "sable_mlp_forward", "sable_mlp_train_step", "sable_plan_exhaustive", "sable_plan_auto", "sable_batch_create", "sable_batch_run",
     "sable_batch_latencies", "sable_batch_destroy", "sable_last_error",
-    "sable_update_values_f64", "sable_spmv_f64", "sable_spmm_f64",
+    "sable_update_values_f64", "sable_spmv_f64", "sable_spmm_f64", "sable_plan_specialize",
 ]
 
 
@@ -70,7 +70,7 @@ class sable_plan_stats(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("plan_ms", ctypes.c_double),
                 ("spmv_variant", ctypes.c_int32), ("spmm_variant", ctypes.c_int32),
                 ("plain_variant", ctypes.c_int32), ("far_split", ctypes.c_int32),
-                ("far_nnz", ctypes.c_int64)]
+                ("far_nnz", ctypes.c_int64), ("spec_ms", ctypes.c_double)]
 
 
 class sable_partition_host(ctypes.Structure):
@@ -124,6 +124,7 @@ def lib():
         "sable_update_values_f64": [P, P, P],
         "sable_spmv_f64": [P, P, P, P],
         "sable_spmm_f64": [P, P, P, i32, P],
+        "sable_plan_specialize": [P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -266,6 +267,10 @@ def sable_spmm(p: Plan, X, Y, n: int, stream=None) -> None:
 
 def sable_update_values(p: Plan, values, stream=None) -> None:
     _check("sable_update_values", lib().sable_update_values(p.h, _ptr(values), _stream(stream)))
+
+
+def sable_plan_specialize(p: Plan, stream=None) -> None:
+    _check("sable_plan_specialize", lib().sable_plan_specialize(p.h, _stream(stream)))
 
 
 def sable_update_values_f64(p: Plan, values, stream=None) -> None:
