@@ -283,7 +283,7 @@ sable_status sable_mlp_train_step(float* params, float* grads, float* m, float* 
                                   float lr, float beta1, float beta2, float eps, int32_t t,
                                   void* stream, float* loss);
 
-/* Exhaustive timed search over the 15 classes (the fallback and judge of the learned
+/* Exhaustive timed search over the 15 classes (the fallback and yardstick of the learned
  * planner): plans A with every class, times its hybrid SpMV on `stream` (after one warm-up,
  * three rounds of `reps` back-to-back launches; the median per-launch average) and returns
  * the fastest plan. x[ncols], y[nrows] are scratch

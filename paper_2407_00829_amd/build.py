@@ -1,7 +1,7 @@
 """Build libsable.so for gfx950 with hipcc (in-tree, no JIT cache).
 
 Every .hip file under csrc/ is compiled to an object in parallel, then linked into
-paper_2407_00829_amd/libsable.so. Called by __graft_entry__.build().
+paper_2407_00829_amd/libsable.so (python -m paper_2407_00829_amd.build).
 """
 from __future__ import annotations
 

@@ -1,6 +1,6 @@
 // Learned planner: matrix features on the GPU, an MLP 140-128-128-15 (forward, backward,
 // Adam) in hand-written kernels, native inference with an exhaustive timed search as the
-// fallback and judge.
+// fallback and yardstick.
 //
 // Label space (15 classes): extractor list {CSR, VDIA+CSR, VBR+CSR, VDIA+VBR+CSR,
 // VBR+VDIA+CSR} x delta {0.5, 0.7, 0.9} (bands and blocks share delta). The plan search of

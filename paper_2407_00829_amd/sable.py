@@ -94,7 +94,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2407_00829_amd.build")
     L = ctypes.CDLL(LIB_PATH)
     P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     sig = {

@@ -1,5 +1,5 @@
 """Live regret of the trained planner (paper_2407_00829_amd/planner_weights.npz) on held-out
-matrices: the exhaustive timed search is the judge; the learned choice must stay close to it
+matrices: the exhaustive timed search is the yardstick; the learned choice must stay close to it
 and beat the fixed default plan on average."""
 import numpy as np
 import pytest
