@@ -29,6 +29,14 @@ constexpr int kBlkDesc = 8;       // ints per staged descriptor
 constexpr int kMmBatch = 3;       // small blocks whose operand loads are issued together
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
+// Packed A fragment (four hi|lo words); read once per product, so loaded non-temporally to
+// leave the caches to X, the operand with reuse.
+__device__ __forceinline__ uint4 ld_afrag(const uint32_t* p) {
+  const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t bf16_rne_dev(float f) {
@@ -142,7 +150,7 @@ __device__ __forceinline__ void mfma_small_batch(const PlanView& P, const int* s
     for (int sl = 0; sl < 2; ++sl) {
       const int arow = r0 + 16 * (ma[s] + sl) + m;
       const int ar = min(max(arow, lo), hi - 1), ak = min(k0 + 4 * kg, w4 - 4);
-      aw[s][sl] = *reinterpret_cast<const uint4*>(P.vbr_mma + mp + (i64)(ar - br0) * w4 + ak);
+      aw[s][sl] = ld_afrag(P.vbr_mma + mp + (i64)(ar - br0) * w4 + ak);
       if (!(sl < nsl[s] && arow >= lo && arow < hi && k0 + 4 * kg < w4)) aw[s][sl] = make_uint4(0u, 0u, 0u, 0u);
     }
   }
@@ -320,7 +328,7 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
         for (int mt = 0; mt < 4; ++mt) {
           const int arow = r0 + 16 * mt + m;
           const int ar = min(max(arow, lo), hi - 1), ak = min(kk, w4 - 4);
-          aw[mt] = *reinterpret_cast<const uint4*>(P.vbr_mma + mp + (i64)(ar - br0) * w4 + ak);
+          aw[mt] = ld_afrag(P.vbr_mma + mp + (i64)(ar - br0) * w4 + ak);
           if (!(arow >= lo && arow < hi && kk < w4)) aw[mt] = make_uint4(0u, 0u, 0u, 0u);
         }
         bf16x4_t bh[2], bl[2];
@@ -371,8 +379,8 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
       T va[8], xa[8], xb[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        cc[u] = P.csr_col[k + u];
-        va[u] = Vals<T>::csr(P)[k + u];
+        cc[u] = __builtin_nontemporal_load(P.csr_col + k + u);
+        va[u] = __builtin_nontemporal_load(Vals<T>::csr(P) + k + u);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -393,8 +401,9 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
       if (okB) a1 += v0 * x0[cB];
     }
     T* yr = Y + (i64)r * n + cb;
-    if (okA) yr[cA] = ys[rl * kMmCols + cA] + a0;
-    if (okB) yr[cB] = ys[rl * kMmCols + cB] + a1;
+    // Y is written once: non-temporal stores keep it from evicting X
+    if (okA) __builtin_nontemporal_store(ys[rl * kMmCols + cA] + a0, yr + cA);
+    if (okB) __builtin_nontemporal_store(ys[rl * kMmCols + cB] + a1, yr + cB);
   }
 }
 
