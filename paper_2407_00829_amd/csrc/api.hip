@@ -127,7 +127,7 @@ void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list
     build_schedule(P, P.sched[k], 256 << k, true, s);
     build_schedule(P, P.sched_plain[k], 256 << k, false, s);
   }
-  build_schedule(P, P.sched_mm, 64, true, s);
+  build_schedule(P, P.sched_mm, 64, true, s, true);
   build_far_split(P, s);
   HIPC(hipStreamSynchronize(s));
   P.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

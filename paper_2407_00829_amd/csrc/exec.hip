@@ -6,7 +6,8 @@
 
 namespace sable {
 
-void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStream_t s);
+void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, bool col_order,
+                 hipStream_t s);
 
 PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool far) {
   PlanView v;
@@ -77,13 +78,16 @@ __global__ void k_blk_tile_counts(const int32_t* __restrict__ blk, int nblk, int
     cnt[b] = (blk[4 * b + 1] - 1) / RT - blk[4 * b] / RT + 1;
 }
 
+// (tile, block) pairs keyed by tile, then by rank[b] (the block's position in the order a
+// tile visits its blocks; the block index itself when rank is null).
 __global__ void k_blk_tile_pairs(const int32_t* __restrict__ blk, const int32_t* __restrict__ off,
-                                 int nblk, int RT, uint64_t* __restrict__ keys,
-                                 int32_t* __restrict__ vals) {
+                                 const int32_t* __restrict__ rank, int nblk, int RT,
+                                 uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
   for (i64 b = blockIdx.x * (i64)blockDim.x + threadIdx.x; b < nblk; b += (i64)gridDim.x * blockDim.x) {
     const int t0 = blk[4 * b] / RT, t1 = (blk[4 * b + 1] - 1) / RT;
+    const uint64_t low = (uint64_t)(uint32_t)(rank ? rank[b] : (int32_t)b);
     for (int t = t0; t <= t1; ++t) {
-      keys[off[b] + (t - t0)] = ((uint64_t)t << 32) | (uint64_t)b;
+      keys[off[b] + (t - t0)] = ((uint64_t)t << 32) | low;
       vals[off[b] + (t - t0)] = (int32_t)b;
     }
   }
@@ -119,6 +123,20 @@ __global__ void k_tile_cost(const int32_t* __restrict__ ptr, int nrows, int RT, 
     }
     cost[t] = c;
   }
+}
+
+// Keys (first column, first row) of every block, for the column-major visiting order.
+__global__ void k_blk_col_keys(const int32_t* __restrict__ blk, int nblk, uint64_t* __restrict__ keys,
+                               int32_t* __restrict__ ids) {
+  for (i64 b = blockIdx.x * (i64)blockDim.x + threadIdx.x; b < nblk; b += (i64)gridDim.x * blockDim.x) {
+    keys[b] = ((uint64_t)(uint32_t)blk[4 * b + 2] << 32) | (uint64_t)(uint32_t)blk[4 * b];
+    ids[b] = (int32_t)b;
+  }
+}
+
+__global__ void k_rank_of(const int32_t* __restrict__ ids, int n, int32_t* __restrict__ rank) {
+  for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    rank[ids[i]] = (int32_t)i;
 }
 
 __global__ void k_zero_i32(int32_t* __restrict__ a, i64 n) {
@@ -335,8 +353,9 @@ __global__ __launch_bounds__(256) void k_spmm_fused_valu(PlanView P, const float
 
 static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s);
 
-void build_schedule(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStream_t s) {
-  build_tiles(P, S, RT, with_formats, s);
+void build_schedule(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStream_t s,
+                    bool col_order) {
+  build_tiles(P, S, RT, with_formats, col_order, s);
   build_order(P, S, with_formats, s);
 }
 
@@ -366,7 +385,10 @@ static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, h
   HIPC(hipStreamSynchronize(s));
 }
 
-void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStream_t s) {
+// col_order: each tile visits its blocks by (first column, first row) instead of block
+// order (SpMM: blocks that read overlapping rows of X run back to back).
+void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, bool col_order,
+                 hipStream_t s) {
   S.rows_per_tile = RT;
   S.ntiles = (P.nrows + RT - 1) / RT;
   const int nt = S.ntiles;
@@ -400,9 +422,20 @@ void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStr
   int32_t npairs = 0;
   HIPC(hipMemcpyAsync(&npairs, off.p + nblk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
+  DBuf<int32_t> rank;
+  if (col_order) {
+    DBuf<uint64_t> ck(nblk);
+    DBuf<int32_t> ids(nblk);
+    k_blk_col_keys<<<grid_for(nblk, 256), 256, 0, s>>>(P.blk.p, nblk, ck.p, ids.p);
+    LAUNCH_CHECK();
+    sort_pairs_u64(ck, ids, nblk, 64, s);
+    rank.alloc(nblk);
+    k_rank_of<<<grid_for(nblk, 256), 256, 0, s>>>(ids.p, nblk, rank.p);
+    LAUNCH_CHECK();
+  }
   DBuf<uint64_t> keys(npairs);
   DBuf<int32_t> vals(npairs);
-  k_blk_tile_pairs<<<grid_for(nblk, 256), 256, 0, s>>>(P.blk.p, off.p, nblk, RT, keys.p, vals.p);
+  k_blk_tile_pairs<<<grid_for(nblk, 256), 256, 0, s>>>(P.blk.p, off.p, rank.p, nblk, RT, keys.p, vals.p);
   LAUNCH_CHECK();
   sort_pairs_u64(keys, vals, npairs, 32 + bits_for((uint64_t)nt), s);
   k_tile_ptr<<<grid_for(nt + 1, 256), 256, 0, s>>>(keys.p, npairs, nt, S.tile_blk_ptr.p);

@@ -143,7 +143,7 @@ bool validate_csr_device(const sable_csr& A, hipStream_t s);
 
 // Schedules and kernels.
 void build_schedule(sable_plan_s& P, Schedule& S, int rows_per_tile, bool with_formats,
-                    hipStream_t s);
+                    hipStream_t s, bool col_order = false);
 void build_bf16_split(sable_plan_s& P, hipStream_t s);
 void build_far_split(sable_plan_s& P, hipStream_t s);
 void refresh_far_values(sable_plan_s& P, hipStream_t s);
