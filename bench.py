@@ -10,7 +10,8 @@ reported separately as plan_ms):
 
 Prints ONE JSON line with value = hybrid GFLOP/s (2 * nnz / t), the roofline of the fused
 kernel (algorithmic bytes per launch / event-timed launch duration vs 8 TB/s), the plain
-CSR baseline, the normwise error against an FP64 reference (scipy.sparse) and the CPU oracle's own rate.
+CSR baseline (this library's autotuned CSR kernels, and ROCm's rocsparse_scsrmv with its
+analysis step as an outside reference; speedup_vs_best_plain_csr uses the faster of them), the normwise error against an FP64 reference (scipy.sparse) and the CPU oracle's own rate.
 
 Other workloads (--workload): c1 (4096^2 mixed, SpMV), c3 (FEM-like SpMM, n=128),
 copy (a plain device copy used to calibrate HBM byte counters).
@@ -89,6 +90,43 @@ def rel_err(y, ref):
     d = np.linalg.norm(y.astype(np.float64) - ref)
     n = np.linalg.norm(ref)
     return float(d / n) if n > 0 else float(d)
+
+
+def rocsparse_csrmv_ms(A, ip, ix, vv, xd, y, steps, warmup, torch):
+    """Reference point: ROCm's own CSR SpMV (rocsparse_scsrmv with its analysis step) on the
+    same matrix and stream; event-timed per launch. Returns (ms, y) or (None, None) when the
+    library is not available."""
+    import ctypes
+    try:
+        L = ctypes.CDLL("librocsparse.so")
+    except OSError:
+        return None, None
+    P, i32 = ctypes.c_void_p, ctypes.c_int32
+
+    def ok(rc, fn):
+        if rc != 0:
+            raise RuntimeError(f"{fn} failed: {rc}")
+
+    h, d, info = P(), P(), P()
+    ok(L.rocsparse_create_handle(ctypes.byref(h)), "create_handle")
+    ok(L.rocsparse_set_stream(h, P(torch.cuda.current_stream().cuda_stream)), "set_stream")
+    ok(L.rocsparse_create_mat_descr(ctypes.byref(d)), "create_mat_descr")
+    ok(L.rocsparse_create_mat_info(ctypes.byref(info)), "create_mat_info")
+    m, n, nnz = i32(A.nrows), i32(A.ncols), i32(A.nnz)
+    op = i32(111)  # rocsparse_operation_none
+    ok(L.rocsparse_scsrmv_analysis(h, op, m, n, nnz, d, P(vv.data_ptr()), P(ip.data_ptr()),
+                                   P(ix.data_ptr()), info), "scsrmv_analysis")
+    one, zero = ctypes.c_float(1.0), ctypes.c_float(0.0)
+
+    def f():
+        ok(L.rocsparse_scsrmv(h, op, m, n, nnz, ctypes.byref(one), d, P(vv.data_ptr()),
+                              P(ip.data_ptr()), P(ix.data_ptr()), info, P(xd.data_ptr()),
+                              ctypes.byref(zero), P(y.data_ptr())), "scsrmv")
+    _, ms = timed_steps(f, steps, warmup, torch)
+    L.rocsparse_destroy_mat_info(info)
+    L.rocsparse_destroy_mat_descr(d)
+    L.rocsparse_destroy_handle(h)
+    return ms, y
 
 
 def cpu_baseline_spmv(A, x, target_s=10.0):
@@ -201,6 +239,10 @@ def run_spmv(args, torch, sable, synth):
     ref_d = torch.from_numpy(ref).cuda()
     err = sable.sable_error_norm_f64(y, ref_d)
     err_p = sable.sable_error_norm_f64(yp, ref_d)
+    ip_, ix_, vv_ = p._src
+    yr = torch.empty(A.nrows, device="cuda")
+    rs_ms, yr = rocsparse_csrmv_ms(A, ip_, ix_, vv_, xd, yr, args.steps, args.warmup, torch)
+    rs_err = sable.sable_error_norm_f64(yr, ref_d) if rs_ms else None
     flush = torch.empty(256 * 1024 * 1024, device="cuda")
     cold = cold_launch_ms(f_h, 30, torch, flush)
     cold_p = cold_launch_ms(f_p, 30, torch, flush)
@@ -233,6 +275,10 @@ def run_spmv(args, torch, sable, synth):
                       "launch_ms": round(ev_ms_p, 5), "rel_err_fp64": err_p,
                       "gbs": round(bytes_p / (ev_ms_p * 1e-3) / 1e9, 1)},
         "speedup_vs_plain_csr": round(ev_ms_p / ev_ms, 4),
+        "speedup_vs_best_plain_csr": round(min(ev_ms_p, rs_ms or ev_ms_p) / ev_ms, 4),
+        "rocsparse_csrmv": None if rs_ms is None else {
+            "launch_ms": round(rs_ms, 5), "gflops": round(2.0 * nnz / (rs_ms * 1e-3) / 1e9, 2),
+            "rel_err_fp64": rs_err, "speedup_hybrid_vs_rocsparse": round(rs_ms / ev_ms, 4)},
         "cold": {"hybrid_launch_ms": round(cold, 5), "plain_launch_ms": round(cold_p, 5),
                  "hybrid_gbs": round(bytes_h / (cold * 1e-3) / 1e9, 1),
                  "hybrid_frac": round(bytes_h / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
