@@ -124,8 +124,8 @@ void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list
   }
   if (P.vbr_cells && (P.flags & SABLE_F_SPLIT_BF16)) build_bf16_split(P, s);
   for (int k = 0; k < 3; ++k) {
-    build_schedule(P, P.sched[k], 256 << k, true, s);
-    build_schedule(P, P.sched_plain[k], 256 << k, false, s);
+    build_schedule(P, P.sched[k], 256 << k, true, s, false, true);
+    build_schedule(P, P.sched_plain[k], 256 << k, false, s, false, true);
   }
   build_schedule(P, P.sched_mm, 64, true, s, true);
   build_far_split(P, s);
@@ -163,7 +163,7 @@ sable::i64 sable_plan_s::device_bytes() const {
   for (int k = 0; k < 7; ++k) {
     const sable::Schedule* S = k < 3 ? &sched[k] : k < 6 ? &sched_plain[k - 3] : &sched_mm;
     b += S->tile_seg_lo.bytes() + S->tile_seg_hi.bytes() + S->tile_blk_ptr.bytes() +
-         S->tile_blk.bytes() + S->order.bytes();
+         S->tile_blk.bytes() + S->order.bytes() + S->row0.bytes();
   }
   b += far.ccol.bytes() + far.far_col.bytes() + far.far_src.bytes() + far.far_val.bytes() +
        far.far_prod.bytes() + far.chunk.bytes();

@@ -30,6 +30,7 @@ struct PlanView {
   const int32_t* tile_blk_ptr;
   const int32_t* tile_blk;
   const int32_t* tile_order;  // launch order of the streamed kernels (may be null)
+  const int32_t* tile_row0;   // tile row bounds (entry-balanced tiling; null: uniform)
   // fp64 copies of the values (FP64 executor; null until set)
   const double* vdia_val64;
   const double* vbr_val64;
@@ -58,6 +59,25 @@ struct Vals<double> {
 // far = true: the view with the far-column split, if the plan has one and it is enabled.
 PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool far = false);
 
+// Rows [r0, rend) of tile t of the view's schedule.
+__device__ __forceinline__ void tile_rows(const PlanView& P, int t, int& r0, int& rend) {
+  if (P.tile_row0) {
+    r0 = P.tile_row0[t];
+    rend = P.tile_row0[t + 1];
+  } else {
+    r0 = t * P.rows_per_tile;
+    rend = min(r0 + P.rows_per_tile, P.nrows);
+  }
+}
+
+// Tile of row r (r < nrows).
+__device__ __forceinline__ int tile_of_row(const PlanView& P, int r) {
+  if (!P.tile_row0) return r / P.rows_per_tile;
+  int l = 0, h = P.ntiles - 1;  // last tile whose first row is <= r
+  while (l < h) { const int m = (l + h + 1) >> 1; if (P.tile_row0[m] <= r) l = m; else h = m - 1; }
+  return l;
+}
+
 
 // ---- SpMV tile body --------------------------------------------------------------------
 // blockDim.x == rows_per_tile threads; thread t owns row tile*rows_per_tile + t for the band
@@ -70,9 +90,10 @@ template <int W>
 __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const float* __restrict__ x,
                                           float* __restrict__ y, float* __restrict__ part) {
   const int RT = P.rows_per_tile;
-  const int r0 = tile * RT;
+  int r0, rend;
+  tile_rows(P, tile, r0, rend);
   const int r = r0 + threadIdx.x;
-  const bool act = r < P.nrows;
+  const bool act = r < rend;
   float acc = 0.f;
   const int slo = P.tile_seg_lo[tile], shi = P.tile_seg_hi[tile];
   for (int s = slo; s < shi; ++s) {
@@ -113,18 +134,18 @@ __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const flo
   for (int rl = grp; rl < RT; rl += ngrp) {
     const int rr = r0 + rl;
     float cs = 0.f;
-    if (rr < P.nrows) {
+    if (rr < rend) {
       const int ke = P.csr_ptr[rr + 1];
       for (int k = P.csr_ptr[rr] + lane; k < ke; k += W) cs += P.csr_val[k] * x[P.csr_col[k]];
     }
 #pragma unroll
     for (int o = W / 2; o > 0; o >>= 1) cs += __shfl_xor(cs, o, W);
-    if (lane == 0 && rr < P.nrows) y[rr] = part[rl] + cs;
+    if (lane == 0 && rr < rend) y[rr] = part[rl] + cs;
   }
 }
 
 // ---- SpMV tile body, streamed variant ---------------------------------------------------
-// Tile = 256*RPT rows, 256 threads; thread t owns rows r0 + t + 256*q (q < RPT).
+// Tile = up to 256*RPT rows, 256 threads; thread t owns rows r0 + t + 256*q (q < RPT).
 //  0. every per-tile index load that depends on nothing else is issued at once, then the
 //     first pass of CSR entries (U per thread: column, value, gathered x), so that the
 //     longest dependent chain of the tile is in flight while the bands run;
@@ -207,9 +228,9 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
   constexpr int kPass = U * kSpmvThreads;
   T* prod = reinterpret_cast<T*>(lds);  // kPass products (lds holds kCsrChunk + RT values of T)
   T* part = prod + kCsrChunk;           // RT block partials
-  const int r0 = tile * RT;
+  int r0, rend;
+  tile_rows(P, tile, r0, rend);
   const int t = threadIdx.x;
-  const int rend = min(r0 + RT, P.nrows);
   // 0. independent loads, then the first CSR pass
   const int e_begin = P.csr_ptr[r0], e_end = P.csr_ptr[rend];
   const int slo = P.tile_seg_lo[tile], shi = P.tile_seg_hi[tile];

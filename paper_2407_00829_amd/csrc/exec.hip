@@ -21,6 +21,7 @@ PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool fa
   v.tile_blk_ptr = S.tile_blk_ptr.p;
   v.tile_blk = S.tile_blk.p;
   v.tile_order = S.order.p;
+  v.tile_row0 = S.row0.p;
   v.vdia_val64 = P.vdia_val64.p;
   v.vbr_val64 = P.vbr_val64.p;
   v.csr_val64 = P.csr_val64.p;
@@ -58,11 +59,31 @@ namespace {
 
 // ---- schedule ----------------------------------------------------------------------------
 
+// Rows [a, b) of tile t: from the row bound table if there is one, else uniform tiles of RT.
+__device__ __forceinline__ void sched_rows(const int32_t* row0, int RT, int nrows, i64 t, int& a, int& b) {
+  if (row0) {
+    a = row0[t];
+    b = row0[t + 1];
+  } else {
+    a = (int)(t * RT);
+    b = (int)min((i64)nrows, (t + 1) * RT);
+  }
+}
+
+// Tile of row r.
+__device__ __forceinline__ int sched_tile(const int32_t* row0, int RT, int ntiles, int r) {
+  if (!row0) return r / RT;
+  int l = 0, h = ntiles - 1;
+  while (l < h) { const int m = (l + h + 1) >> 1; if (row0[m] <= r) l = m; else h = m - 1; }
+  return l;
+}
+
 __global__ void k_tile_segs(const int32_t* __restrict__ srs, const int32_t* __restrict__ snr,
-                            int nseg, int RT, int ntiles, int nrows, int32_t* __restrict__ lo,
-                            int32_t* __restrict__ hi) {
+                            int nseg, int RT, const int32_t* __restrict__ row0, int ntiles,
+                            int nrows, int32_t* __restrict__ lo, int32_t* __restrict__ hi) {
   for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < ntiles; t += (i64)gridDim.x * blockDim.x) {
-    const int a = (int)(t * RT), b = (int)min((i64)nrows, (t + 1) * RT);
+    int a, b;
+    sched_rows(row0, RT, nrows, t, a, b);
     int l = 0, h = nseg;  // first segment whose end > a (ends are sorted: segments disjoint)
     while (l < h) { int m = (l + h) >> 1; if (srs[m] + snr[m] <= a) l = m + 1; else h = m; }
     lo[t] = l;
@@ -73,18 +94,21 @@ __global__ void k_tile_segs(const int32_t* __restrict__ srs, const int32_t* __re
 }
 
 __global__ void k_blk_tile_counts(const int32_t* __restrict__ blk, int nblk, int RT,
+                                  const int32_t* __restrict__ row0, int ntiles,
                                   int32_t* __restrict__ cnt) {
   for (i64 b = blockIdx.x * (i64)blockDim.x + threadIdx.x; b < nblk; b += (i64)gridDim.x * blockDim.x)
-    cnt[b] = (blk[4 * b + 1] - 1) / RT - blk[4 * b] / RT + 1;
+    cnt[b] = sched_tile(row0, RT, ntiles, blk[4 * b + 1] - 1) - sched_tile(row0, RT, ntiles, blk[4 * b]) + 1;
 }
 
 // (tile, block) pairs keyed by tile, then by rank[b] (the block's position in the order a
 // tile visits its blocks; the block index itself when rank is null).
 __global__ void k_blk_tile_pairs(const int32_t* __restrict__ blk, const int32_t* __restrict__ off,
                                  const int32_t* __restrict__ rank, int nblk, int RT,
+                                 const int32_t* __restrict__ row0, int ntiles,
                                  uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
   for (i64 b = blockIdx.x * (i64)blockDim.x + threadIdx.x; b < nblk; b += (i64)gridDim.x * blockDim.x) {
-    const int t0 = blk[4 * b] / RT, t1 = (blk[4 * b + 1] - 1) / RT;
+    const int t0 = sched_tile(row0, RT, ntiles, blk[4 * b]);
+    const int t1 = sched_tile(row0, RT, ntiles, blk[4 * b + 1] - 1);
     const uint64_t low = (uint64_t)(uint32_t)(rank ? rank[b] : (int32_t)b);
     for (int t = t0; t <= t1; ++t) {
       keys[off[b] + (t - t0)] = ((uint64_t)t << 32) | low;
@@ -105,14 +129,16 @@ __global__ void k_tile_ptr(const uint64_t* __restrict__ keys, i64 n, int ntiles,
 
 // Estimated cost of each tile: CSR entries (weight 2: index, value and a gathered x) plus
 // VBR cells plus VDIA cells of the tile.
-__global__ void k_tile_cost(const int32_t* __restrict__ ptr, int nrows, int RT, int ntiles,
+__global__ void k_tile_cost(const int32_t* __restrict__ ptr, int nrows, int RT,
+                            const int32_t* __restrict__ row0, int ntiles,
                             const int32_t* __restrict__ slo, const int32_t* __restrict__ shi,
                             const int32_t* __restrict__ srs, const int32_t* __restrict__ snr,
                             const int32_t* __restrict__ snd, const int32_t* __restrict__ bptr,
                             const int32_t* __restrict__ tblk, const int32_t* __restrict__ blk,
                             i64* __restrict__ cost) {
   for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < ntiles; t += (i64)gridDim.x * blockDim.x) {
-    const int a = (int)(t * RT), b = (int)min((i64)nrows, (t + 1) * RT);
+    int a, b;
+    sched_rows(row0, RT, nrows, t, a, b);
     i64 c = 2 * (i64)(ptr[b] - ptr[a]);
     if (slo)
       for (int s = slo[t]; s < shi[t]; ++s)
@@ -319,7 +345,7 @@ __global__ __launch_bounds__(256) void k_spmm_fused_valu(PlanView P, const float
     }
     if (s >= 0 && r >= P.seg_row_start[s] + P.seg_nrows[s]) s = -1;
   }
-  const int tile = r / P.rows_per_tile;
+  const int tile = tile_of_row(P, r);
   for (int cb = 0; cb < n; cb += 64) {
     const int c = cb + lane;
     const bool ok = c < n;
@@ -354,7 +380,27 @@ __global__ __launch_bounds__(256) void k_spmm_fused_valu(PlanView P, const float
 static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s);
 
 void build_schedule(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStream_t s,
-                    bool col_order) {
+                    bool col_order, bool balance) {
+  S.row0.reset();
+  if (balance && P.nrows > 0) {  // entry-balanced tile bounds from the CSR row pointers
+    std::vector<int32_t> ptr, r0;
+    to_host(ptr, with_formats ? P.csr_ptr.p : P.a_ptr.p, (size_t)P.nrows + 1, s);
+    const i64 emax = std::max<i64>(4096, 8 * (i64)RT);
+    bool split = false;
+    for (int r = 0; r < P.nrows;) {
+      int r1 = std::min(P.nrows, r + RT);
+      if (ptr[r1] - ptr[r] > emax) {  // largest r1 > r with at most emax entries (>= 1 row)
+        int lo = r + 1, hi = r1;
+        while (lo < hi) { const int m = (lo + hi + 1) / 2; if (ptr[m] - ptr[r] <= emax) lo = m; else hi = m - 1; }
+        r1 = lo;
+        split = true;
+      }
+      r0.push_back(r);
+      r = r1;
+    }
+    r0.push_back(P.nrows);
+    if (split) to_dev(S.row0, r0, s);  // uniform tiling already balanced: keep it implicit
+  }
   build_tiles(P, S, RT, with_formats, col_order, s);
   build_order(P, S, with_formats, s);
 }
@@ -365,7 +411,7 @@ static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, h
   DBuf<i64> cost(nt);
   const bool fm = with_formats && P.nseg;
   k_tile_cost<<<grid_for(nt, 256), 256, 0, s>>>(
-      with_formats ? P.csr_ptr.p : P.a_ptr.p, P.nrows, S.rows_per_tile, nt,
+      with_formats ? P.csr_ptr.p : P.a_ptr.p, P.nrows, S.rows_per_tile, S.row0.p, nt,
       fm ? S.tile_seg_lo.p : nullptr, fm ? S.tile_seg_hi.p : nullptr, P.seg_row_start.p,
       P.seg_nrows.p, P.seg_ndiags.p, S.tile_blk_ptr.p, S.tile_blk.p,
       with_formats ? P.blk.p : nullptr, cost.p);
@@ -390,7 +436,7 @@ static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, h
 void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, bool col_order,
                  hipStream_t s) {
   S.rows_per_tile = RT;
-  S.ntiles = (P.nrows + RT - 1) / RT;
+  S.ntiles = S.row0.p ? (int)S.row0.n - 1 : (P.nrows + RT - 1) / RT;
   const int nt = S.ntiles;
   S.tile_seg_lo.alloc(nt);
   S.tile_seg_hi.alloc(nt);
@@ -399,8 +445,9 @@ void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, bool c
   const int nblk = with_formats ? P.nblk : 0;
   if (nt) {
     if (nseg) {
-      k_tile_segs<<<grid_for(nt, 256), 256, 0, s>>>(P.seg_row_start.p, P.seg_nrows.p, nseg, RT, nt,
-                                                    P.nrows, S.tile_seg_lo.p, S.tile_seg_hi.p);
+      k_tile_segs<<<grid_for(nt, 256), 256, 0, s>>>(P.seg_row_start.p, P.seg_nrows.p, nseg, RT,
+                                                    S.row0.p, nt, P.nrows, S.tile_seg_lo.p,
+                                                    S.tile_seg_hi.p);
     } else {
       k_zero_i32<<<grid_for(nt, 256), 256, 0, s>>>(S.tile_seg_lo.p, nt);
       LAUNCH_CHECK();
@@ -416,7 +463,7 @@ void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, bool c
     return;
   }
   DBuf<int32_t> cnt(nblk), off(nblk + 1);
-  k_blk_tile_counts<<<grid_for(nblk, 256), 256, 0, s>>>(P.blk.p, nblk, RT, cnt.p);
+  k_blk_tile_counts<<<grid_for(nblk, 256), 256, 0, s>>>(P.blk.p, nblk, RT, S.row0.p, nt, cnt.p);
   LAUNCH_CHECK();
   exclusive_scan_i32(cnt.p, off.p, nblk, s);
   int32_t npairs = 0;
@@ -435,7 +482,8 @@ void build_tiles(sable_plan_s& P, Schedule& S, int RT, bool with_formats, bool c
   }
   DBuf<uint64_t> keys(npairs);
   DBuf<int32_t> vals(npairs);
-  k_blk_tile_pairs<<<grid_for(nblk, 256), 256, 0, s>>>(P.blk.p, off.p, rank.p, nblk, RT, keys.p, vals.p);
+  k_blk_tile_pairs<<<grid_for(nblk, 256), 256, 0, s>>>(P.blk.p, off.p, rank.p, nblk, RT, S.row0.p,
+                                                       nt, keys.p, vals.p);
   LAUNCH_CHECK();
   sort_pairs_u64(keys, vals, npairs, 32 + bits_for((uint64_t)nt), s);
   k_tile_ptr<<<grid_for(nt + 1, 256), 256, 0, s>>>(keys.p, npairs, nt, S.tile_blk_ptr.p);

@@ -73,6 +73,11 @@ struct Schedule {
   // XCD's contiguous run of slots the tiles are sorted by estimated cost, heaviest first, so
   // the few expensive tiles (dense blocks, long rows) do not finish last.
   DBuf<int32_t> order;
+  // Entry-balanced tiling (SpMV schedules): tile t is rows [row0[t], row0[t+1]), at most
+  // rows_per_tile rows and, unless it is a single row, at most max(4096, 8 rows_per_tile)
+  // CSR entries, so a run of long rows is spread over several workgroups. Empty: tile t is
+  // rows [t rows_per_tile, (t+1) rows_per_tile).
+  DBuf<int32_t> row0;
 };
 
 }  // namespace sable
@@ -143,7 +148,7 @@ bool validate_csr_device(const sable_csr& A, hipStream_t s);
 
 // Schedules and kernels.
 void build_schedule(sable_plan_s& P, Schedule& S, int rows_per_tile, bool with_formats,
-                    hipStream_t s, bool col_order = false);
+                    hipStream_t s, bool col_order = false, bool balance = false);
 void build_bf16_split(sable_plan_s& P, hipStream_t s);
 void build_far_split(sable_plan_s& P, hipStream_t s);
 void refresh_far_values(sable_plan_s& P, hipStream_t s);
