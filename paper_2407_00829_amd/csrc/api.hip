@@ -109,26 +109,39 @@ void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list
     HIPC(hipMemcpyAsync(P.a_col.p, A.indices, A.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     HIPC(hipMemcpyAsync(P.a_val.p, A.values, A.nnz * sizeof(float), hipMemcpyDeviceToDevice, s));
   }
-  Resid R;
-  resid_from_input(R, A, s);
-  for (int e = 0; e < nlist; ++e) {
-    if (list[e].kind == SABLE_X_CSR) {
-      extract_csr(P, R, s);
-      break;
+  if (A.nrows == 0 || A.ncols == 0) {
+    // no entry can exist: the plan is an empty CSR part (products give y = 0, or nothing)
+    P.csr_nnz = 0;
+    P.csr_ptr.alloc(A.nrows + 1);
+    P.csr_col.alloc(0);
+    P.csr_val.alloc(0);
+    HIPC(hipMemsetAsync(P.csr_ptr.p, 0, (A.nrows + 1) * sizeof(int32_t), s));
+    for (int e = 0; e < nlist && list[e].kind != SABLE_X_CSR; ++e)
+      if (list[e].kind == SABLE_X_VBR) blocks_none(P, th, list[e].vbr_mode);
+  } else {
+    Resid R;
+    resid_from_input(R, A, s);
+    for (int e = 0; e < nlist; ++e) {
+      if (list[e].kind == SABLE_X_CSR) {
+        extract_csr(P, R, s);
+        break;
+      }
+      DBuf<uint8_t> claimed(R.nnz);
+      if (R.nnz) HIPC(hipMemsetAsync(claimed.p, 0, R.nnz, s));
+      if (list[e].kind == SABLE_X_VDIA) extract_bands(P, R, th, claimed, s);
+      else extract_blocks(P, R, th, list[e].vbr_mode, claimed, s);
+      resid_compact(R, claimed, s);
     }
-    DBuf<uint8_t> claimed(R.nnz);
-    if (R.nnz) HIPC(hipMemsetAsync(claimed.p, 0, R.nnz, s));
-    if (list[e].kind == SABLE_X_VDIA) extract_bands(P, R, th, claimed, s);
-    else extract_blocks(P, R, th, list[e].vbr_mode, claimed, s);
-    resid_compact(R, claimed, s);
+    if (P.vbr_cells && (P.flags & SABLE_F_SPLIT_BF16)) build_bf16_split(P, s);
   }
-  if (P.vbr_cells && (P.flags & SABLE_F_SPLIT_BF16)) build_bf16_split(P, s);
-  for (int k = 0; k < 3; ++k) {
-    build_schedule(P, P.sched[k], 256 << k, true, s, false, true);
-    build_schedule(P, P.sched_plain[k], 256 << k, false, s, false, true);
+  if (A.nrows > 0) {  // every product entry point returns at once when nrows == 0
+    for (int k = 0; k < 3; ++k) {
+      build_schedule(P, P.sched[k], 256 << k, true, s, false, true);
+      build_schedule(P, P.sched_plain[k], 256 << k, false, s, false, true);
+    }
+    build_schedule(P, P.sched_mm, 64, true, s, true);
+    build_far_split(P, s);
   }
-  build_schedule(P, P.sched_mm, 64, true, s, true);
-  build_far_split(P, s);
   HIPC(hipStreamSynchronize(s));
   P.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_spmv_stream(PlanView P, const float* __
 // multiplies its entries by x values read from LDS.
 __global__ __launch_bounds__(kFarThreads) void k_far_gather(const int32_t* __restrict__ chunk,
                                                            int per_xcd, int ncols,
-                                                           const int32_t* __restrict__ col,
+                                                           const uint16_t* __restrict__ col,
                                                            const float* __restrict__ val,
                                                            const float* __restrict__ x,
                                                            float* __restrict__ prod) {
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kFarThreads) void k_far_gather(const int32_t* __res
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int k = b + t + kFarThreads * u;
-    j[u] = k < e ? __builtin_nontemporal_load(col + k) - base : 0;
+    j[u] = k < e ? (int)__builtin_nontemporal_load(col + k) : 0;
     a[u] = k < e ? __builtin_nontemporal_load(val + k) : 0.f;
   }
   // slice: all loads of a thread in flight together (float4 when x is 16-byte aligned)

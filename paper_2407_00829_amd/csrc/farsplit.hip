@@ -39,14 +39,15 @@ __global__ void k_far_keys(const int32_t* __restrict__ col, const int32_t* __res
   }
 }
 
-// Sorted position q of far entry k = idx[q]: copy column and value, encode -(1 + q).
+// Sorted position q of far entry k = idx[q]: copy the column within its panel and the value,
+// encode -(1 + q).
 __global__ void k_far_fill(const int32_t* __restrict__ idx, i64 nfar, const int32_t* __restrict__ col,
-                           const float* __restrict__ val, int32_t* __restrict__ fcol,
-                           float* __restrict__ fval, int32_t* __restrict__ fsrc,
-                           int32_t* __restrict__ ccol) {
+                           const float* __restrict__ val, int panel_cols,
+                           uint16_t* __restrict__ fcol, float* __restrict__ fval,
+                           int32_t* __restrict__ fsrc, int32_t* __restrict__ ccol) {
   for (i64 q = blockIdx.x * (i64)blockDim.x + threadIdx.x; q < nfar; q += (i64)gridDim.x * blockDim.x) {
     const int k = idx[q];
-    fcol[q] = col[k];
+    fcol[q] = (uint16_t)(col[k] % panel_cols);
     fval[q] = val[k];
     fsrc[q] = k;
     ccol[k] = (int32_t)(-1 - q);
@@ -100,8 +101,8 @@ void build_far_split(sable_plan_s& P, hipStream_t s) {
   F.far_val.alloc(nfar);
   F.far_src.alloc(nfar);
   F.far_prod.alloc(nfar);
-  k_far_fill<<<grid_for(nfar, 256), 256, 0, s>>>(idx.p, nfar, P.csr_col.p, P.csr_val.p, F.far_col.p,
-                                                  F.far_val.p, F.far_src.p, F.ccol.p);
+  k_far_fill<<<grid_for(nfar, 256), 256, 0, s>>>(idx.p, nfar, P.csr_col.p, P.csr_val.p, panel_cols,
+                                                  F.far_col.p, F.far_val.p, F.far_src.p, F.ccol.p);
   LAUNCH_CHECK();
   DBuf<int32_t> pp(npanel + 1);
   k_panel_ptr<<<grid_for(npanel + 1, 256), 256, 0, s>>>(keys.p, nfar, npanel, pp.p);

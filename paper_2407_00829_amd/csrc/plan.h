@@ -48,10 +48,11 @@ struct ExecParams {
 // equal those without the split bit for bit.
 constexpr int kFarWindow = 1 << 17;      // |column - row| above this is far
 constexpr int kFarPanelCols = 1 << 13;   // x slice per panel: 32 KB of fp32 in LDS
-constexpr int kFarThreads = 512;
+constexpr int kFarThreads = 1024;
 constexpr int kFarChunk = 8 * kFarThreads;  // entries per gather workgroup
 constexpr int kFarMinEntries = 1 << 16;  // below this the extra pass is not worth a launch
 constexpr int kFarMinCols = 1 << 20;     // x below 4 MB stays L2-resident anyway
+static_assert(kFarPanelCols <= 65536, "panel-relative far columns are 16-bit");
 
 struct FarSplit {
   int npanel = 0;  // 0: no split
@@ -59,7 +60,8 @@ struct FarSplit {
   int per_xcd = 0;  // gather workgroups per XCD
   i64 nfar = 0;
   DBuf<int32_t> ccol;                 // csr_col with far entries encoded as -(1 + q)
-  DBuf<int32_t> far_col, far_src;     // panel-major (row order within a panel); src = CSR index
+  DBuf<uint16_t> far_col;             // column within its panel; panel-major, row order inside
+  DBuf<int32_t> far_src;              // CSR index of each far entry
   DBuf<float> far_val, far_prod;
   DBuf<int32_t> chunk;  // [8][per_xcd] (begin, end) entry ranges, begin < 0 = none
 };
@@ -136,6 +138,8 @@ namespace sable {
 // Extractors (each claims entries of R, fills its part of the plan, marks claimed[k]).
 void extract_bands(sable_plan_s& P, const Resid& R, const sable_thresholds& th,
                    DBuf<uint8_t>& claimed, hipStream_t s);
+// What extract_blocks records (mode used, tile size) for an input that has no entries.
+void blocks_none(sable_plan_s& P, const sable_thresholds& th, int mode);
 void extract_blocks(sable_plan_s& P, const Resid& R, const sable_thresholds& th, int mode,
                     DBuf<uint8_t>& claimed, hipStream_t s);
 void extract_csr(sable_plan_s& P, const Resid& R, hipStream_t s);

@@ -537,14 +537,22 @@ std::vector<TrimOut> tiled_for_T(const Resid& R, const DBuf<int32_t>& rows,
   return out;
 }
 
+const int kTileSizes[5] = {4, 6, 8, 16, 32};
+
+// Tile size reported for a residual without entries: the largest size in the candidate set.
+int tile_for_empty(const sable_thresholds& th) {
+  for (int t = 4; t >= 0; --t)
+    if (!th.tile_set_mask || (th.tile_set_mask & (1 << t))) return kTileSizes[t];
+  return 0;
+}
+
 std::vector<TrimOut> blocks_tiled(const Resid& R, const sable_thresholds& th, int& chosen,
                                   hipStream_t s) {
-  static const int Ts[5] = {4, 6, 8, 16, 32};
+  const int* Ts = kTileSizes;
   chosen = 0;
   std::vector<TrimOut> best;
   if (R.nnz == 0) {
-    for (int t = 4; t >= 0; --t)
-      if (!th.tile_set_mask || (th.tile_set_mask & (1 << t))) { chosen = Ts[t]; break; }
+    chosen = tile_for_empty(th);
     return best;
   }
   DBuf<int32_t> rows;
@@ -567,6 +575,12 @@ bool paper_fits(i64 nrows, i64 ncols) {
 }  // namespace
 
 bool vbr_paper_fits(i64 nrows, i64 ncols) { return paper_fits(nrows, ncols); }
+
+void blocks_none(sable_plan_s& P, const sable_thresholds& th, int mode) {
+  if (mode == SABLE_VBR_AUTO) mode = paper_fits(P.nrows, P.ncols) ? SABLE_VBR_PAPER : SABLE_VBR_TILED;
+  P.vbr_mode_used = mode;
+  P.vbr_tile = mode == SABLE_VBR_TILED ? tile_for_empty(th) : 0;
+}
 
 void extract_blocks(sable_plan_s& P, const Resid& R, const sable_thresholds& th, int mode,
                     DBuf<uint8_t>& claimed, hipStream_t s) {

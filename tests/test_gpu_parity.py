@@ -164,6 +164,38 @@ def test_empty_and_degenerate():
             assert np.allclose(y.cpu().numpy(), oracle.spmv(A, x), rtol=1e-5, atol=1e-6)
 
 
+@pytest.mark.parametrize("shape", [(0, 5), (5, 0), (0, 0), (9, 9)])
+def test_no_rows_columns_or_entries(shape):
+    """Empty shapes: the partition export matches the oracle's (all formats empty), every
+    product entry point (hybrid, plain CSR, SpMM, FP64, autotuned) writes y = 0 or nothing,
+    and the planner features are finite."""
+    nr, nc = shape
+    A = synth.from_coo(nr, nc, [], [], [])
+    th = oracle.Thresholds(lseg=2, amin_band=2, amin_block=4)
+    for kinds in PLANS:
+        for mode in (oracle.MODE_PAPER, oracle.MODE_TILED):
+            p = gpu_plan(A, kinds, mode, th)
+            assert_same_partition(sable.sable_plan_export(p), oracle.plan(A, kinds, mode, th))
+            x = torch.zeros(nc, device="cuda")
+            y = torch.full((nr,), float("nan"), device="cuda")
+            sable.sable_spmv(p, x, y)
+            yp = torch.full((nr,), float("nan"), device="cuda")
+            sable.sable_csr_spmv(p, x, yp)
+            X = torch.zeros((nc, 3), device="cuda")
+            Y = torch.full((nr, 3), float("nan"), device="cuda")
+            sable.sable_spmm(p, X, Y, 3)
+            sable.sable_update_values_f64(p, torch.zeros(0, dtype=torch.float64, device="cuda"))
+            y64 = torch.full((nr,), float("nan"), dtype=torch.float64, device="cuda")
+            sable.sable_spmv_f64(p, x.double(), y64)
+            sable.sable_autotune(p, 0, 1, x, y)
+            sable.sable_spmv(p, x, y)
+            torch.cuda.synchronize()
+            for t in (y, yp, Y, y64):
+                assert bool((t == 0).all())
+    ip, ix, vv = sable.device_csr(A)
+    assert np.isfinite(sable.sable_features(nr, nc, ip, ix, vv)).all()
+
+
 def test_invalid_csr_rejected():
     A = synth.from_coo(4, 4, [0, 1], [0, 1], [1.0, 2.0])
     ip, ix, vv = sable.device_csr(A)
