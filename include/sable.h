@@ -311,8 +311,12 @@ typedef struct {
   float* y;        /* y or Y (device) */
 } sable_batch_item;
 
-/* Concatenate the work of count plans into one persistent kernel captured in a hipGraph.
- * The plans and operands must outlive the batch. */
+/* Concatenate the work of count plans into persistent kernels captured in one hipGraph:
+ * SpMV items run the 256-row streamed tile (the plan's SpMV variant 0, whatever variant it
+ * holds), SpMM items the fused SpMM tile in the plan's mode; each item's result is bitwise
+ * equal to that standalone launch. Items without rows do nothing and complete at the start.
+ * The plans and operands must outlive the batch. Errors: SABLE_ERR_INVALID_ARG for a bad
+ * item (op, n, NULL or misaligned operands), SABLE_ERR_TOO_LARGE past 2^31 work units. */
 sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_item* items,
                                 int32_t count, void* stream, sable_batch_t* out);
 /* Launch the captured graph on `stream` (asynchronous). */

@@ -1,11 +1,14 @@
-// Batched persistent execution of many plans in one launch, captured in a hipGraph.
+// Batched persistent execution of many plans, captured in a hipGraph.
 //
-// Work units are (item, tile) pairs laid out item by item. A persistent grid (every CU,
-// a few workgroups each) pulls units from one atomic counter; a unit runs exactly the tile
-// body of the standalone product (streamed SpMV tiles, or SpMM tiles), so each item's
-// result is bitwise equal to its standalone launch with the same kernel variant. The last
-// unit of an item stamps the GPU wall clock. A reset kernel (no memset nodes) clears the
-// counters and stamps the batch start; both kernels are captured once and replayed.
+// Work units are (item, tile) pairs laid out item by item, SpMV items and SpMM items in two
+// lists. Two persistent kernels, one per list, each with a grid of every CU times its
+// resident workgroups, pull units from their own atomic counter; a unit runs exactly the tile
+// body of the standalone product, so each item's result is bitwise equal to its standalone
+// launch with the same kernel (SpMV: the 256-row streamed tile, variant 0; SpMM: the fused
+// tile in the plan's matrix-core mode). Keeping the two apart lets each run at the occupancy
+// of its standalone kernel. The last unit of an item stamps the GPU wall clock. A reset kernel
+// (no memset nodes) clears the counters and stamps the batch start; the three kernels are
+// captured once and replayed.
 #include <algorithm>
 
 #include "exec.h"
@@ -14,7 +17,7 @@
 namespace sable {
 
 struct BatchItemDev {
-  int op, n, rpt, mfma;
+  int op, n, mfma, units;
   int units_per_col, col_chunks;  // SpMM: row tiles x column chunks
   const float* x;
   float* y;
@@ -23,46 +26,55 @@ struct BatchItemDev {
 namespace {
 
 __global__ void k_batch_reset(unsigned* __restrict__ counter, unsigned* __restrict__ done,
-                              int count, unsigned long long* __restrict__ stamps) {
-  for (int i = threadIdx.x; i < count; i += blockDim.x) done[i] = 0;
+                              const BatchItemDev* __restrict__ items, int count,
+                              unsigned long long* __restrict__ stamps) {
+  __shared__ unsigned long long t0;
   if (threadIdx.x == 0) {
     counter[0] = 0;
-    stamps[count] = wall_clock64();
+    counter[1] = 0;
+    t0 = wall_clock64();
+    stamps[count] = t0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    done[i] = 0;
+    if (items[i].units == 0) stamps[i] = t0;  // nothing to run: complete at the start
   }
 }
 
-constexpr int kBatchLds = kMmRows * kMmCols + kMmBlkStage * kBlkDesc;  // >= largest SpMV tile
-static_assert(kBatchLds >= kCsrChunk + 1024, "LDS budget");
+constexpr int kBatchSpmvLds = kCsrChunk + kSpmvThreads;  // spmv_tile_stream<1>
+constexpr int kBatchSpmmLds = kMmRows * kMmCols + kMmBlkStage * kBlkDesc;
 
-__global__ __launch_bounds__(256, 3) void k_batch(const PlanView* __restrict__ views,
-                                               const BatchItemDev* __restrict__ items,
-                                               const i64* __restrict__ unit_off, int count,
-                                               i64 total, unsigned* __restrict__ counter,
-                                               unsigned* __restrict__ done,
-                                               unsigned long long* __restrict__ stamps) {
-  __shared__ float lds[kBatchLds];  // exactly 40 KB: four workgroups per CU
+// Units of one list: list[k] is the item of the k-th entry, off[k] its first unit.
+template <int OP>
+__device__ __forceinline__ void batch_units(const PlanView* __restrict__ views,
+                                            const BatchItemDev* __restrict__ items,
+                                            const int32_t* __restrict__ list,
+                                            const i64* __restrict__ off, int nlist, i64 total,
+                                            unsigned* __restrict__ counter,
+                                            unsigned* __restrict__ done,
+                                            unsigned long long* __restrict__ stamps, float* lds) {
   unsigned* unit = reinterpret_cast<unsigned*>(lds);  // broadcast slot, free between units
   for (;;) {
     __syncthreads();  // the previous unit is done with the LDS
     if (threadIdx.x == 0) unit[0] = atomicAdd(counter, 1u);
     __syncthreads();
-    const i64 u = (i64)unit[0];
+    // uniform across the workgroup: scalar registers for the unit, its item and its view
+    const i64 u = (i64)(unsigned)__builtin_amdgcn_readfirstlane((int)unit[0]);
     __syncthreads();  // every thread has read the slot before the unit body reuses it
     if (u >= total) break;
-    int lo = 0, hi = count - 1;  // item of unit u
+    int lo = 0, hi = nlist - 1;  // last list entry whose first unit is <= u
     while (lo < hi) {
       int m = (lo + hi + 1) >> 1;
-      if (unit_off[m] <= u) lo = m; else hi = m - 1;
+      if (off[m] <= u) lo = m; else hi = m - 1;
     }
-    const int it = lo;
+    const int it = list[lo];
     const BatchItemDev I = items[it];
     const PlanView& P = views[it];
-    int local = (int)(u - unit_off[it]);
-    if (I.op == 0) {
+    int local = (int)(u - off[lo]);
+    if constexpr (OP == 0) {
       if (P.tile_order) local = P.tile_order[local];
-      if (I.rpt == 1) spmv_tile_stream<1>(P, local, I.x, I.y, lds);
-      else if (I.rpt == 2) spmv_tile_stream<2>(P, local, I.x, I.y, lds);
-      else spmv_tile_stream<4>(P, local, I.x, I.y, lds);
+      spmv_tile_stream<1>(P, local, I.x, I.y, lds);
     } else {
       int rt = local % I.units_per_col;
       const int cc = local / I.units_per_col;
@@ -70,12 +82,33 @@ __global__ __launch_bounds__(256, 3) void k_batch(const PlanView* __restrict__ v
       spmm_tile(P, rt * kMmRows, cc * kMmCols, I.n, I.x, I.y, lds, I.mfma);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const unsigned units = (unsigned)(unit_off[it + 1] - unit_off[it]);
-      if (atomicAdd(&done[it], 1u) + 1u == units) stamps[it] = wall_clock64();
-    }
+    // completion count only: nothing in the kernel reads another unit's output, so no
+    // fence (on this chip a device-scope release writes back the whole L2)
+    if (threadIdx.x == 0 && atomicAdd(&done[it], 1u) + 1u == (unsigned)I.units)
+      stamps[it] = wall_clock64();
   }
+}
+
+__global__ __launch_bounds__(256) void k_batch_spmv(const PlanView* __restrict__ views,
+                                                    const BatchItemDev* __restrict__ items,
+                                                    const int32_t* __restrict__ list,
+                                                    const i64* __restrict__ off, int nlist,
+                                                    i64 total, unsigned* __restrict__ counter,
+                                                    unsigned* __restrict__ done,
+                                                    unsigned long long* __restrict__ stamps) {
+  __shared__ float lds[kBatchSpmvLds];
+  batch_units<0>(views, items, list, off, nlist, total, counter, done, stamps, lds);
+}
+
+__global__ __launch_bounds__(256, 3) void k_batch_spmm(const PlanView* __restrict__ views,
+                                                       const BatchItemDev* __restrict__ items,
+                                                       const int32_t* __restrict__ list,
+                                                       const i64* __restrict__ off, int nlist,
+                                                       i64 total, unsigned* __restrict__ counter,
+                                                       unsigned* __restrict__ done,
+                                                       unsigned long long* __restrict__ stamps) {
+  __shared__ float lds[kBatchSpmmLds];  // 40 KB
+  batch_units<1>(views, items, list, off, nlist, total, counter, done, stamps, lds);
 }
 
 }  // namespace
@@ -86,7 +119,8 @@ struct sable_batch_s {
   int count = 0;
   sable::DBuf<sable::PlanView> views;
   sable::DBuf<sable::BatchItemDev> items;
-  sable::DBuf<sable::i64> unit_off;
+  sable::DBuf<int32_t> list[2];     // SpMV items, SpMM items
+  sable::DBuf<sable::i64> off[2];   // first unit of each list entry, total at the end
   sable::DBuf<unsigned> counter, done;
   sable::DBuf<unsigned long long> stamps;
   hipStream_t cap = nullptr;
@@ -126,7 +160,8 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
     B->count = count;
     std::vector<PlanView> hv(count);
     std::vector<BatchItemDev> hi(count);
-    std::vector<i64> off(count + 1, 0);
+    std::vector<int32_t> lists[2];
+    std::vector<i64> offs[2] = {{0}, {0}};
     for (int i = 0; i < count; ++i) {
       const sable_plan_s& P = *plans[i];
       const sable_batch_item& it = items[i];
@@ -137,26 +172,36 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
       d.x = it.x;
       d.y = it.y;
       i64 units = 0;
-      if (it.op == 0) {
-        const int var = P.prm.spmv_variant <= 2 ? P.prm.spmv_variant : 0;
-        d.rpt = 1 << var;
-        hv[i] = make_view(P, P.sched[var], false);
-        units = hv[i].ntiles;
-      } else {
-        hv[i] = make_view(P, P.sched_mm, false);
-        d.units_per_col = (P.nrows + kMmRows - 1) / kMmRows;
-        d.col_chunks = (it.n + kMmCols - 1) / kMmCols;
-        d.mfma = spmm_mfma_mode(P);
-        units = (i64)d.units_per_col * d.col_chunks;
+      if (P.nrows > 0) {
+        if (it.op == 0) {
+          hv[i] = make_view(P, P.sched[0], false);
+          units = hv[i].ntiles;
+        } else {
+          hv[i] = make_view(P, P.sched_mm, false);
+          d.units_per_col = (P.nrows + kMmRows - 1) / kMmRows;
+          d.col_chunks = (it.n + kMmCols - 1) / kMmCols;
+          d.mfma = spmm_mfma_mode(P);
+          units = (i64)d.units_per_col * d.col_chunks;
+        }
       }
+      if (units > INT32_MAX) SB_THROW(SABLE_ERR_TOO_LARGE, "item %d: %lld work units", i, (long long)units);
+      d.units = (int)units;
       hi[i] = d;
-      off[i + 1] = off[i] + units;
+      if (units) {
+        lists[it.op].push_back(i);
+        offs[it.op].push_back(offs[it.op].back() + units);
+      }
     }
-    const i64 total = off[count];
+    const i64 total[2] = {offs[0].back(), offs[1].back()};
+    if (total[0] + total[1] > (i64)UINT32_MAX / 2) SB_THROW(SABLE_ERR_TOO_LARGE, "too many work units");
     to_dev(B->views, hv, s);
     to_dev(B->items, hi, s);
-    to_dev(B->unit_off, off, s);
-    B->counter.alloc(1);
+    for (int k = 0; k < 2; ++k) {
+      lists[k].push_back(-1);  // never read: keeps the arrays non-empty
+      to_dev(B->list[k], lists[k], s);
+      to_dev(B->off[k], offs[k], s);
+    }
+    B->counter.alloc(2);
     B->done.alloc(count);
     B->stamps.alloc(count + 1);
     HIPC(hipStreamSynchronize(s));
@@ -165,14 +210,24 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
     HIPC(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIPC(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     B->tick_hz = (double)khz * 1e3;
-    int per_cu = 0;  // resident workgroups per CU for this kernel (registers and LDS)
-    HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, 256, 0));
-    const unsigned grid = (unsigned)std::max<i64>(1, std::min<i64>(total, (i64)cus * std::max(1, per_cu)));
+    // resident workgroups per CU of each kernel (registers and LDS) size its grid
+    int per_cu[2] = {0, 0};
+    HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[0], k_batch_spmv, 256, 0));
+    HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[1], k_batch_spmm, 256, 0));
+    unsigned grid[2];
+    for (int k = 0; k < 2; ++k)
+      grid[k] = (unsigned)std::max<i64>(1, std::min<i64>(total[k], (i64)cus * std::max(1, per_cu[k])));
     HIPC(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
     HIPC(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
-    k_batch_reset<<<1, 256, 0, B->cap>>>(B->counter.p, B->done.p, count, B->stamps.p);
-    k_batch<<<grid, 256, 0, B->cap>>>(B->views.p, B->items.p, B->unit_off.p, count, total,
-                                      B->counter.p, B->done.p, B->stamps.p);
+    k_batch_reset<<<1, 256, 0, B->cap>>>(B->counter.p, B->done.p, B->items.p, count, B->stamps.p);
+    if (total[0])
+      k_batch_spmv<<<grid[0], 256, 0, B->cap>>>(B->views.p, B->items.p, B->list[0].p, B->off[0].p,
+                                                (int)lists[0].size() - 1, total[0], B->counter.p,
+                                                B->done.p, B->stamps.p);
+    if (total[1])
+      k_batch_spmm<<<grid[1], 256, 0, B->cap>>>(B->views.p, B->items.p, B->list[1].p, B->off[1].p,
+                                                (int)lists[1].size() - 1, total[1], B->counter.p + 1,
+                                                B->done.p, B->stamps.p);
     hipError_t ce = hipStreamEndCapture(B->cap, &B->graph);
     if (ce != hipSuccess) SB_THROW(SABLE_ERR_HIP, "stream capture: %s", hipGetErrorString(ce));
     HIPC(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));

@@ -45,54 +45,91 @@ __global__ void k_run_flags(const uint32_t* __restrict__ skey, const int32_t* __
     flag[p] = (p == 0 || skey[p] != skey[p - 1] || srow[p] != srow[p - 1] + 1) ? 1 : 0;
 }
 
-// rid_incl[p] = number of run starts in [0, p]; the run of position p is rid_incl[p] - 1
-__global__ void k_run_len(const int32_t* __restrict__ rid_incl, i64 n, int32_t* __restrict__ len) {
-  for (i64 p = blockIdx.x * (i64)blockDim.x + threadIdx.x; p < n; p += (i64)gridDim.x * blockDim.x)
-    atomicAdd(&len[rid_incl[p] - 1], 1);
+// Block-private counters in LDS, merged into global memory with one atomic per nonzero
+// counter per block (global atomics on a few shared addresses serialise).
+template <int NB>
+__device__ __forceinline__ void lds_zero(unsigned long long* h) {
+  for (int i = threadIdx.x; i < NB; i += blockDim.x) h[i] = 0;
+  __syncthreads();
 }
 
-__global__ void k_run_hist(const int32_t* __restrict__ len, i64 nruns,
+template <int NB>
+__device__ __forceinline__ void lds_merge_add(const unsigned long long* h, unsigned long long* g) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < NB; i += blockDim.x)
+    if (h[i]) atomicAdd(&g[i], h[i]);
+}
+
+// run r starts at start[r]: rid[p] (exclusive scan of the run-start flags) numbers the runs
+__global__ void k_run_starts(const int32_t* __restrict__ flag, const int32_t* __restrict__ rid,
+                             i64 n, int32_t* __restrict__ start) {
+  for (i64 p = blockIdx.x * (i64)blockDim.x + threadIdx.x; p < n; p += (i64)gridDim.x * blockDim.x)
+    if (flag[p]) start[rid[p]] = (int32_t)p;
+}
+
+// hist[log_bin(L)] += L over the run lengths L
+__global__ void k_run_hist(const int32_t* __restrict__ start, i64 nruns, i64 n,
                            unsigned long long* __restrict__ hist) {
-  for (i64 r = blockIdx.x * (i64)blockDim.x + threadIdx.x; r < nruns; r += (i64)gridDim.x * blockDim.x)
-    atomicAdd(&hist[log_bin(len[r])], (unsigned long long)len[r]);
+  __shared__ unsigned long long h[64];
+  lds_zero<64>(h);
+  for (i64 r = blockIdx.x * (i64)blockDim.x + threadIdx.x; r < nruns; r += (i64)gridDim.x * blockDim.x) {
+    const i64 L = (r + 1 < nruns ? (i64)start[r + 1] : n) - start[r];
+    atomicAdd(&h[log_bin(L)], (unsigned long long)L);
+  }
+  lds_merge_add<64>(h, hist);
 }
 
 __global__ void k_tile_hist(const uint64_t* __restrict__ uniq, const int32_t* __restrict__ cnt,
                             i64 nt, i64 ntc, int nrows, int ncols,
                             unsigned long long* __restrict__ hist,
                             unsigned long long* __restrict__ dense_nnz) {
+  __shared__ unsigned long long h[65];  // 64 density bins, nnz in half-dense tiles
+  lds_zero<65>(h);
   for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < nt; t += (i64)gridDim.x * blockDim.x) {
     const i64 I = (i64)(uniq[t] / (uint64_t)ntc), J = (i64)(uniq[t] % (uint64_t)ntc);
-    const i64 h = min((I + 1) * 16, (i64)nrows) - I * 16;
+    const i64 hh = min((I + 1) * 16, (i64)nrows) - I * 16;
     const i64 w = min((J + 1) * 16, (i64)ncols) - J * 16;
     const i64 c = cnt[t];
-    int b = (int)((64 * c) / (h * w));
+    int b = (int)((64 * c) / (hh * w));
     if (b > 63) b = 63;
-    atomicAdd(&hist[b], (unsigned long long)c);
-    if (2 * c >= h * w) atomicAdd(dense_nnz, (unsigned long long)c);
+    atomicAdd(&h[b], (unsigned long long)c);
+    if (2 * c >= hh * w) atomicAdd(&h[64], (unsigned long long)c);
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 65; i += blockDim.x)
+    if (h[i]) atomicAdd(i < 64 ? &hist[i] : dense_nnz, h[i]);
 }
 
 __global__ void k_diag_stats(const uint32_t* __restrict__ uniq, const int32_t* __restrict__ cnt,
                              i64 nd, int nrows, unsigned long long* __restrict__ out) {
   // out[0] = nnz on d = 0, out[1] = nnz with |d| <= 32, out[2] = max count
+  __shared__ unsigned long long h[3];
+  lds_zero<3>(h);
   for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < nd; t += (i64)gridDim.x * blockDim.x) {
     const i64 d = (i64)uniq[t] - (nrows - 1);
-    if (d == 0) atomicAdd(&out[0], (unsigned long long)cnt[t]);
-    if (d >= -32 && d <= 32) atomicAdd(&out[1], (unsigned long long)cnt[t]);
-    atomicMax(&out[2], (unsigned long long)cnt[t]);
+    if (d == 0) atomicAdd(&h[0], (unsigned long long)cnt[t]);
+    if (d >= -32 && d <= 32) atomicAdd(&h[1], (unsigned long long)cnt[t]);
+    atomicMax(&h[2], (unsigned long long)cnt[t]);
   }
+  __syncthreads();
+  if (threadIdx.x < 2 && h[threadIdx.x]) atomicAdd(&out[threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x == 2 && h[2]) atomicMax(&out[2], h[2]);
 }
 
 __global__ void k_row_stats(const int32_t* __restrict__ ptr, int nrows,
                             unsigned long long* __restrict__ out) {
   // out[0] = sum len^2, out[1] = max len, out[2] = empty rows
+  __shared__ unsigned long long h[3];
+  lds_zero<3>(h);
   for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < nrows; i += (i64)gridDim.x * blockDim.x) {
     const unsigned long long L = (unsigned long long)(ptr[i + 1] - ptr[i]);
-    atomicAdd(&out[0], L * L);
-    atomicMax(&out[1], L);
-    if (L == 0) atomicAdd(&out[2], 1ull);
+    atomicAdd(&h[0], L * L);
+    atomicMax(&h[1], L);
+    if (L == 0) atomicAdd(&h[2], 1ull);
   }
+  __syncthreads();
+  if ((threadIdx.x == 0 || threadIdx.x == 2) && h[threadIdx.x]) atomicAdd(&out[threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x == 1 && h[1]) atomicMax(&out[1], h[1]);
 }
 
 }  // namespace
@@ -124,31 +161,30 @@ void compute_features(const sable_csr& A, hipStream_t s, float* out) {
     int32_t nruns = 0;
     HIPC(hipMemcpyAsync(&nruns, rid.p + nnz, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    DBuf<int32_t> len(nruns);
-    HIPC(hipMemsetAsync(len.p, 0, nruns * sizeof(int32_t), s));
-    k_run_len<<<grid_for(nnz, 256), 256, 0, s>>>(rid.p + 1, nnz, len.p);
+    DBuf<int32_t> start(nruns);
+    k_run_starts<<<grid_for(nnz, 256), 256, 0, s>>>(flag.p, rid.p, nnz, start.p);
     LAUNCH_CHECK();
     // hist: [0,64) run lengths, [64,128) tile densities, 128..130 diagonal stats,
     // 131..133 row stats, 134 nnz in half-dense tiles
     DBuf<unsigned long long> hist(135);
     HIPC(hipMemsetAsync(hist.p, 0, hist.bytes(), s));
-    k_run_hist<<<grid_for(nruns, 256), 256, 0, s>>>(len.p, nruns, hist.p);
+    k_run_hist<<<grid_for(nruns, 256, 1024), 256, 0, s>>>(start.p, nruns, nnz, hist.p);
     LAUNCH_CHECK();
     // diagonal counts
     DBuf<uint32_t> du;
     DBuf<int32_t> dc;
     ndiag = rle_u32(dkey.p, nnz, du, dc, s);
-    k_diag_stats<<<grid_for(ndiag, 256), 256, 0, s>>>(du.p, dc.p, ndiag, n, hist.p + 128);
+    k_diag_stats<<<grid_for(ndiag, 256, 1024), 256, 0, s>>>(du.p, dc.p, ndiag, n, hist.p + 128);
     LAUNCH_CHECK();
     // tiles of 16 x 16
     sort_pairs_u64(tkey, dummy, nnz, bits_for((uint64_t)(ntr * ntc)), s);
     DBuf<uint64_t> tu;
     DBuf<int32_t> tc;
     const i64 nt = rle_u64(tkey.p, nnz, tu, tc, s);
-    k_tile_hist<<<grid_for(nt, 256), 256, 0, s>>>(tu.p, tc.p, nt, ntc, n, m, hist.p + 64,
+    k_tile_hist<<<grid_for(nt, 256, 1024), 256, 0, s>>>(tu.p, tc.p, nt, ntc, n, m, hist.p + 64,
                                                   hist.p + 134);
     LAUNCH_CHECK();
-    if (n) k_row_stats<<<grid_for(n, 256), 256, 0, s>>>(R.ptr.p, n, hist.p + 131);
+    if (n) k_row_stats<<<grid_for(n, 256, 1024), 256, 0, s>>>(R.ptr.p, n, hist.p + 131);
     LAUNCH_CHECK();
     std::vector<unsigned long long> h;
     to_host(h, hist.p, hist.n, s);

@@ -1,5 +1,6 @@
-"""Batched persistent hipGraph launch: every item bitwise equal to its standalone launch,
-across several graph replays with eager work in between; latencies are recorded."""
+"""Batched persistent hipGraph launch: every item bitwise equal to its standalone launch with
+the same tile kernel, across several graph replays with eager work in between; latencies are
+recorded; items without rows complete at once."""
 import numpy as np
 import pytest
 
@@ -38,11 +39,16 @@ def make_items(count, seed=0):
 
 
 def standalone(plans, items):
+    """Standalone results with the kernels a batch runs: SpMV items with the 256-row streamed
+    tile (variant 0, whatever variant the plan holds), SpMM items as planned."""
     outs = []
     for p, (op, n, x, y) in zip(plans, items):
         z = torch.empty_like(y)
         if op == 0:
+            v = sable.sable_plan_info(p)["spmv_variant"]
+            sable.sable_plan_set_variant(p, 0, 0)
             sable.sable_spmv(p, x, z)
+            sable.sable_plan_set_variant(p, 0, v)
         else:
             sable.sable_spmm(p, x, z, n)
         outs.append(z)
@@ -63,6 +69,26 @@ def test_batch_bitwise_equal_and_replays():
             assert torch.equal(y, r), (rep, i)
         ticks, hz = sable.sable_batch_latencies(b)
         assert hz > 0 and np.all(ticks > 0)
+    b.destroy()
+
+
+def test_batch_with_empty_items():
+    plans, items = make_items(6, seed=3)
+    E = synth.from_coo(0, 7, [], [], [])
+    pe = sable.plan_host(E, [sable.SABLE_X_VDIA, sable.SABLE_X_VBR, sable.SABLE_X_CSR],
+                         sable.SABLE_VBR_TILED, sable.Thresholds())
+    ye = torch.zeros(0, device="cuda")
+    plans = plans[:3] + [pe] + plans[3:]
+    items = items[:3] + [(0, 1, torch.zeros(7, device="cuda"), ye)] + items[3:]
+    ref = standalone(plans, items)
+    b = sable.sable_batch_create(plans, items)
+    for rep in range(2):
+        sable.sable_batch_run(b)
+        torch.cuda.synchronize()
+        for i, ((_, _, _, y), r) in enumerate(zip(items, ref)):
+            assert torch.equal(y, r), (rep, i)
+        ticks, hz = sable.sable_batch_latencies(b)
+        assert ticks[3] == 0 and np.all(np.delete(ticks, 3) > 0)
     b.destroy()
 
 
