@@ -92,6 +92,37 @@ def rel_err(y, ref):
     return float(d / n) if n > 0 else float(d)
 
 
+def graph_ms(make, reps, torch):
+    """Per-launch time of `reps` launches captured in one graph and replayed: the GPU's own
+    time for kernels of a few microseconds, without the host's per-launch cost. `make()`
+    returns the launch callable; it is built inside the capture so that it launches on the
+    capturing stream."""
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        make()()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        f = make()
+        for _ in range(reps):
+            f()
+    g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    best = None
+    for _ in range(3):
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        best = ms if best is None else min(best, ms)
+    del g
+    return best
+
+
 def rocsparse_csrmv_ms(A, ip, ix, vv, xd, y, steps, warmup, torch):
     """Reference point: ROCm's own CSR SpMV (rocsparse_scsrmv with its analysis step) on the
     same matrix and stream; event-timed per launch. Returns (ms, y) or (None, None) when the
@@ -118,10 +149,14 @@ def rocsparse_csrmv_ms(A, ip, ix, vv, xd, y, steps, warmup, torch):
                                    P(ix.data_ptr()), info), "scsrmv_analysis")
     one, zero = ctypes.c_float(1.0), ctypes.c_float(0.0)
 
-    def f():
-        ok(L.rocsparse_scsrmv(h, op, m, n, nnz, ctypes.byref(one), d, P(vv.data_ptr()),
-                              P(ip.data_ptr()), P(ix.data_ptr()), info, P(xd.data_ptr()),
-                              ctypes.byref(zero), P(y.data_ptr())), "scsrmv")
+    cargs = (h, op, m, n, nnz, ctypes.byref(one), d, P(vv.data_ptr()), P(ip.data_ptr()),
+             P(ix.data_ptr()), info, P(xd.data_ptr()), ctypes.byref(zero), P(y.data_ptr()))
+    fn = L.rocsparse_scsrmv
+
+    def f():  # arguments marshalled once, as for the library's own launches
+        rc = fn(*cargs)
+        if rc != 0:
+            ok(rc, "scsrmv")
     _, ms = timed_steps(f, steps, warmup, torch)
     L.rocsparse_destroy_mat_info(info)
     L.rocsparse_destroy_mat_descr(d)
@@ -231,8 +266,8 @@ def run_spmv(args, torch, sable, synth):
     elif args.autotune:
         sable.sable_autotune(p, 0, 1, xd, y)
     info = sable.sable_plan_info(p)
-    f_h = lambda: sable.sable_spmv(p, xd, y)  # noqa: E731
-    f_p = lambda: sable.sable_csr_spmv(p, xd, yp)  # noqa: E731
+    f_h = sable.launcher("sable_spmv", p, xd, y)
+    f_p = sable.launcher("sable_csr_spmv", p, xd, yp)
     wall, ev_ms = timed_steps(f_h, args.steps, args.warmup, torch)
     wall_p, ev_ms_p = timed_steps(f_p, args.steps, args.warmup, torch)
     ref = ref_spmv(A, x)
@@ -309,12 +344,12 @@ def run_spmv_f64(args, torch, sable, synth):
     best = None
     for v in (0, 1, 2):  # streamed tile sizes
         sable.sable_plan_set_variant(p, 0, v)
-        _, t = timed_steps(lambda: sable.sable_spmv_f64(p, xd, y), 20, 5, torch)
+        _, t = timed_steps(sable.launcher("sable_spmv_f64", p, xd, y), 20, 5, torch)
         if best is None or t < best[1]:
             best = (v, t)
     sable.sable_plan_set_variant(p, 0, best[0])
     info = sable.sable_plan_info(p)
-    f_h = lambda: sable.sable_spmv_f64(p, xd, y)  # noqa: E731
+    f_h = sable.launcher("sable_spmv_f64", p, xd, y)
     wall, ev_ms = timed_steps(f_h, args.steps, args.warmup, torch)
     err = rel_err(y.cpu().numpy(), ref_spmv(A, x))  # values and x are fp32-representable
     bytes_h = (8 * info["vdia_cells"] + 20 * info["nseg"] + 8 * info["vbr_cells"]
@@ -354,7 +389,7 @@ def run_spmm(args, torch, sable, synth):
     log(f"[bench] plan: {info}")
     Xd = torch.from_numpy(X).cuda()
     Y = torch.empty(A.nrows, n, device="cuda")
-    f_h = lambda: sable.sable_spmm(p, Xd, Y, n)  # noqa: E731
+    f_h = sable.launcher("sable_spmm", p, Xd, Y, n)
     wall, ev_ms = timed_steps(f_h, args.steps, args.warmup, torch)
     rows = np.random.default_rng(0).choice(A.nrows, 4096, replace=False)
     ref = ref_spmm_rows(A, X, rows)
@@ -426,12 +461,12 @@ def run_batch(args, torch, sable, synth):
     def run_batch_once():
         sable.sable_batch_run(b)
 
+    seq = [sable.launcher("sable_spmv", p, x, y) if op == 0 else
+           sable.launcher("sable_spmm", p, x, y, n) for p, (op, n, x, y) in zip(plans, items)]
+
     def run_sequential():
-        for p, (op, n, x, y) in zip(plans, items):
-            if op == 0:
-                sable.sable_spmv(p, x, y)
-            else:
-                sable.sable_spmm(p, x, y, n)
+        for f in seq:
+            f()
 
     wall_b, ev_b = timed_steps(run_batch_once, args.steps, args.warmup, torch)
     run_batch_once()
@@ -443,11 +478,8 @@ def run_batch(args, torch, sable, synth):
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(plans) + 1)]
     torch.cuda.synchronize()
     evs[0].record()
-    for k, (p, (op, n, x, y)) in enumerate(zip(plans, items)):
-        if op == 0:
-            sable.sable_spmv(p, x, y)
-        else:
-            sable.sable_spmm(p, x, y, n)
+    for k, f in enumerate(seq):
+        f()
         evs[k + 1].record()
     torch.cuda.synchronize()
     lat_s = np.array([evs[0].elapsed_time(e) * 1e3 for e in evs[1:]])
@@ -500,7 +532,7 @@ def run_spec(args, torch, sable, synth):
         x = torch.from_numpy(synth.gen_dense_vector(i, A.ncols)).cuda()
         y = torch.empty(A.nrows, device="cuda")
         sable.sable_autotune(p, 0, 1, x, y)
-        _, t_gen = timed_steps(lambda: sable.sable_spmv(p, x, y), 50, 10, torch)
+        _, t_gen = timed_steps(sable.launcher("sable_spmv", p, x, y), 50, 10, torch)
         try:
             sable.sable_plan_specialize(p)
         except sable.SableError:
@@ -508,7 +540,7 @@ def run_spec(args, torch, sable, synth):
             continue
         comp.append(sable.sable_plan_info(p)["spec_ms"])
         sable.sable_plan_set_variant(p, 0, 11)
-        _, t_spec = timed_steps(lambda: sable.sable_spmv(p, x, y), 50, 10, torch)
+        _, t_spec = timed_steps(sable.launcher("sable_spmv", p, x, y), 50, 10, torch)
         ratios.append(t_gen / t_spec)
         p.destroy()
     r = np.array(ratios)
@@ -517,6 +549,72 @@ def run_spec(args, torch, sable, synth):
             "spec_faster_fraction": float(np.mean(r > 1.0)),
             "speedup_p10_p50_p90": [float(v) for v in np.percentile(r, [10, 50, 90])],
             "compile_ms_median": float(np.median(comp))}
+
+
+def run_coverage(args, torch, sable, synth):
+    """Block-coverage cutoff sweep, the paper's coverage-threshold table (Appendix, Tab.
+    threshold) on generated matrices: --count matrices from the planner's generator (band /
+    block / scatter mixes), each planned as [VBR, CSR] (tiled search, paper defaults delta
+    0.5, A_min 2500) without a coverage cutoff; coverage = VBR nnz / nnz. SpMV: the autotuned
+    plan against this library's autotuned plain CSR kernel; SpMM (n = 128): against the
+    autotuned CSR-only plan. These kernels take microseconds, so each is timed as a captured
+    graph of --steps launches (GPU time without the host's per-launch cost); rocSPARSE csrmv,
+    which is not captured, is reported per matrix with ordinary back-to-back event timing.
+    For each cutoff t the matrices with coverage >= t are included, with the count of
+    speedups > 1 and <= 1 and their geometric mean."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    from paper_2407_00829_amd import planner
+    seeds = [300000 + args.seed * 100000 + i for i in range(args.count)]
+    with cf.ProcessPoolExecutor(8) as ex:
+        mats = list(ex.map(planner.make_matrix, seeds))
+    log(f"[bench] generated {len(mats)} matrices")
+    n_rhs = 128
+    cov, sv, sm, times = [], [], [], []
+    for i, (_, A, x) in enumerate(mats):
+        p = sable.plan_host(A, [sable.SABLE_X_VBR, sable.SABLE_X_CSR], sable.SABLE_VBR_TILED,
+                            sable.Thresholds(coverage_pm=0))
+        q = sable.plan_host(A, [sable.SABLE_X_CSR], sable.SABLE_VBR_TILED, sable.Thresholds())
+        cov.append(sable.sable_plan_info(p)["vbr_nnz"] / max(A.nnz, 1))
+        xd = torch.from_numpy(x).cuda()
+        y = torch.empty(A.nrows, device="cuda")
+        sable.sable_autotune(p, 0, 1, xd, y)
+        t_h = graph_ms(lambda: sable.launcher("sable_spmv", p, xd, y), args.steps, torch)
+        t_p = graph_ms(lambda: sable.launcher("sable_csr_spmv", p, xd, y), args.steps, torch)
+        ip, ix, vv = p._src
+        t_r, _ = rocsparse_csrmv_ms(A, ip, ix, vv, xd, torch.empty_like(y), args.steps,
+                                    args.warmup, torch)
+        sv.append(t_p / t_h)
+        times.append([t_h, t_p, t_r])
+        X = torch.from_numpy(synth.gen_dense_matrix(i, A.ncols, n_rhs)).cuda()
+        Y = torch.empty(A.nrows, n_rhs, device="cuda")
+        sable.sable_autotune(p, 1, n_rhs, X, Y)
+        sable.sable_autotune(q, 1, n_rhs, X, Y)
+        t_hm = graph_ms(lambda: sable.launcher("sable_spmm", p, X, Y, n_rhs), args.steps, torch)
+        t_qm = graph_ms(lambda: sable.launcher("sable_spmm", q, X, Y, n_rhs), args.steps, torch)
+        sm.append(t_qm / t_hm)
+        p.destroy()
+        q.destroy()
+        if (i + 1) % 20 == 0:
+            log(f"[bench] {i + 1} matrices timed")
+    cov, sv, sm = np.array(cov), np.array(sv), np.array(sm)
+    table = []
+    for t in list(range(0, 16)) + [20]:
+        m = cov >= t / 100.0
+        row = {"threshold_pct": t, "matrices": int(m.sum())}
+        for name, r in (("spmv", sv[m]), ("spmm", sm[m])):
+            row[name] = {"faster": int((r > 1.0).sum()), "not_faster": int((r <= 1.0).sum()),
+                         "geomean": float(np.exp(np.mean(np.log(r)))) if r.size else None}
+        table.append(row)
+    return {"workload": "coverage", "matrices": len(cov), "spmm_n": n_rhs,
+            "coverage_p10_p50_p90": [float(v) for v in np.percentile(cov, [10, 50, 90])],
+            "table": table,
+            "per_matrix": [[round(float(c), 4), round(float(a), 4), round(float(b), 4)]
+                           for c, a, b in zip(cov, sv, sm)],
+            "spmv_ms_hybrid_plain_rocsparse": [[round(v, 5) if v else None for v in t]
+                                               for t in times]}
 
 
 def run_copy(args, torch):
@@ -537,7 +635,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "batch", "spec", "copy"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "batch", "spec", "coverage", "copy"])
     ap.add_argument("--count", type=int, default=256)
     ap.add_argument("--plan", default="hybrid", choices=["hybrid", "vbr"])
     ap.add_argument("--seed", type=int, default=0)
@@ -569,6 +667,8 @@ def main():
         out = run_batch(args, torch, sable, synth)
     elif args.workload == "spec":
         out = run_spec(args, torch, sable, synth)
+    elif args.workload == "coverage":
+        out = run_coverage(args, torch, sable, synth)
     else:
         out = run_copy(args, torch)
     print(json.dumps(out), flush=True)

@@ -140,6 +140,7 @@ void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list
       build_schedule(P, P.sched_plain[k], 256 << k, false, s, false, true);
     }
     build_schedule(P, P.sched_mm, 64, true, s, true);
+    for (int k = 0; k < 4; ++k) build_schedule(P, P.sched_w[k], 128 >> k, true, s);
     build_far_split(P, s);
   }
   HIPC(hipStreamSynchronize(s));
@@ -173,8 +174,9 @@ sable::i64 sable_plan_s::device_bytes() const {
   b += csr_ptr.bytes() + csr_col.bytes() + csr_val.bytes();
   b += vdia_val64.bytes() + vbr_val64.bytes() + csr_val64.bytes();
   b += a_ptr.bytes() + a_col.bytes() + a_val.bytes() + owner.bytes() + slot.bytes();
-  for (int k = 0; k < 7; ++k) {
-    const sable::Schedule* S = k < 3 ? &sched[k] : k < 6 ? &sched_plain[k - 3] : &sched_mm;
+  for (int k = 0; k < 11; ++k) {
+    const sable::Schedule* S = k < 3 ? &sched[k] : k < 6 ? &sched_plain[k - 3] : k == 6 ? &sched_mm
+                                                                                       : &sched_w[k - 7];
     b += S->tile_seg_lo.bytes() + S->tile_seg_hi.bytes() + S->tile_blk_ptr.bytes() +
          S->tile_blk.bytes() + S->order.bytes() + S->row0.bytes();
   }

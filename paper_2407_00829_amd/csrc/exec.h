@@ -80,12 +80,13 @@ __device__ __forceinline__ int tile_of_row(const PlanView& P, int r) {
 
 
 // ---- SpMV tile body --------------------------------------------------------------------
-// blockDim.x == rows_per_tile threads; thread t owns row tile*rows_per_tile + t for the band
-// and block parts (lane per row: diagonal-major / column-major values are contiguous across
-// consecutive rows). The CSR part then runs W lanes per row with a shuffle reduction; the
-// per-row band+block partial goes through LDS. Every row's sum has a fixed order:
-// y = (sum over segments, diagonals ascending + sum over blocks, columns ascending)
-//     + (CSR entries in index order, reduced by a fixed xor tree).
+// 256 threads over a tile of rows_per_tile <= 256 rows (256 / W rows in the W-lanes
+// schedules); thread t owns row r0 + t for the band part (lane per row: diagonal-major values
+// are contiguous across consecutive rows), and for blocks when W == 1. For W > 1 each row's
+// W lanes take its block columns (c0 + lane, c0 + lane + W, ...) and then its CSR entries,
+// and a shuffle reduction adds them; the band partial goes through LDS. Every row's sum has a
+// fixed order: W == 1: (bands, diagonals ascending + blocks, columns ascending) + CSR in
+// index order; W > 1: bands + (per lane: blocks, then CSR, strided by W; xor tree over lanes).
 template <int W>
 __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const float* __restrict__ x,
                                           float* __restrict__ y, float* __restrict__ part) {
@@ -109,14 +110,16 @@ __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const flo
     }
   }
   const int blo = P.tile_blk_ptr[tile], bhi = P.tile_blk_ptr[tile + 1];
-  for (int q = blo; q < bhi; ++q) {
-    const int b = P.tile_blk[q];
-    const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
-    if (act && r >= br0 && r < br1) {
-      const int c0 = P.blk[4 * b + 2], c1 = P.blk[4 * b + 3];
-      const int h = br1 - br0;
-      const float* v = P.vbr_val + P.blk_val_ptr[b] + (r - br0);
-      for (int c = c0; c < c1; ++c) acc += v[(i64)(c - c0) * h] * x[c];
+  if (W == 1) {  // blocks lane per row (W > 1: by the row's W lanes, with its CSR entries)
+    for (int q = blo; q < bhi; ++q) {
+      const int b = P.tile_blk[q];
+      const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
+      if (act && r >= br0 && r < br1) {
+        const int c0 = P.blk[4 * b + 2], c1 = P.blk[4 * b + 3];
+        const int h = br1 - br0;
+        const float* v = P.vbr_val + P.blk_val_ptr[b] + (r - br0);
+        for (int c = c0; c < c1; ++c) acc += v[(i64)(c - c0) * h] * x[c];
+      }
     }
   }
   if (W == 1) {
@@ -130,11 +133,20 @@ __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const flo
   __syncthreads();
   const int lane = threadIdx.x & (W - 1);
   const int grp = threadIdx.x / W;
-  const int ngrp = RT / W;
+  const int ngrp = (int)blockDim.x / W;  // row groups of W lanes
   for (int rl = grp; rl < RT; rl += ngrp) {
     const int rr = r0 + rl;
     float cs = 0.f;
     if (rr < rend) {
+      for (int q = blo; q < bhi; ++q) {  // block columns c0 + lane, c0 + lane + W, ...
+        const int b = P.tile_blk[q];
+        const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
+        if (rr < br0 || rr >= br1) continue;
+        const int c0 = P.blk[4 * b + 2], c1 = P.blk[4 * b + 3];
+        const int h = br1 - br0;
+        const float* v = P.vbr_val + P.blk_val_ptr[b] + (rr - br0);
+        for (int c = c0 + lane; c < c1; c += W) cs += v[(i64)(c - c0) * h] * x[c];
+      }
       const int ke = P.csr_ptr[rr + 1];
       for (int k = P.csr_ptr[rr] + lane; k < ke; k += W) cs += P.csr_val[k] * x[P.csr_col[k]];
     }

@@ -385,7 +385,11 @@ void build_schedule(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hip
   if (balance && P.nrows > 0) {  // entry-balanced tile bounds from the CSR row pointers
     std::vector<int32_t> ptr, r0;
     to_host(ptr, with_formats ? P.csr_ptr.p : P.a_ptr.p, (size_t)P.nrows + 1, s);
-    const i64 emax = std::max<i64>(4096, 8 * (i64)RT);
+    // at most max(4096, 8 RT) entries per tile; on small inputs fewer (down to 512), so that
+    // there are about 2048 tiles (8 per CU) and no workgroup carries a long serial chain
+    const i64 total = ptr[P.nrows];
+    const i64 emax = std::min<i64>(std::max<i64>(4096, 8 * (i64)RT),
+                                   std::max<i64>(512, (total + 2047) / 2048));
     bool split = false;
     for (int r = 0; r < P.nrows;) {
       int r1 = std::min(P.nrows, r + RT);
@@ -553,7 +557,8 @@ void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s)
     launch_k_spmv_stream(v, 1 << k, var >= 8, x, y, s);
     return;
   }
-  const PlanView v = make_view(P, P.sched[0], false);
+  // W lanes per CSR row: tiles of 256 / W rows, so every thread of a workgroup has a row
+  const PlanView v = make_view(P, var == 3 ? P.sched[0] : P.sched_w[var - 4], false);
   const unsigned nb = (unsigned)v.ntiles;
   switch (var) {
     case 3: k_spmv_fused<1><<<nb, 256, 0, s>>>(v, x, y); break;

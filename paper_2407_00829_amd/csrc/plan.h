@@ -76,9 +76,10 @@ struct Schedule {
   // the few expensive tiles (dense blocks, long rows) do not finish last.
   DBuf<int32_t> order;
   // Entry-balanced tiling (SpMV schedules): tile t is rows [row0[t], row0[t+1]), at most
-  // rows_per_tile rows and, unless it is a single row, at most max(4096, 8 rows_per_tile)
-  // CSR entries, so a run of long rows is spread over several workgroups. Empty: tile t is
-  // rows [t rows_per_tile, (t+1) rows_per_tile).
+  // rows_per_tile rows and, unless it is a single row, at most
+  // min(max(4096, 8 rows_per_tile), max(512, CSR entries / 2048)) CSR entries, so a run of
+  // long rows is spread over several workgroups and a small input still gives about 2048
+  // tiles. Empty: tile t is rows [t rows_per_tile, (t+1) rows_per_tile).
   DBuf<int32_t> row0;
 };
 
@@ -121,6 +122,7 @@ struct sable_plan_s {
   sable::Schedule sched[3];        // tiles of 256, 512, 1024 rows with the formats
   sable::Schedule sched_plain[3];  // the same tilings for the whole input as CSR
   sable::Schedule sched_mm;        // 64-row tiles of the fused SpMM
+  sable::Schedule sched_w[4];      // tiles of 256 / W rows, W = 2, 4, 8, 16 lanes per CSR row
   sable::FarSplit far;             // far-column split of the CSR part (streamed SpMV)
   sable::ExecParams prm;
   uint32_t flags = 0;

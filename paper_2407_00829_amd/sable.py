@@ -265,6 +265,22 @@ def sable_spmm(p: Plan, X, Y, n: int, stream=None) -> None:
     _check("sable_spmm", lib().sable_spmm(p.h, _ptr(X), _ptr(Y), int(n), _stream(stream)))
 
 
+def launcher(fn: str, p: Plan, *args, stream=None):
+    """A zero-argument callable for repeated calls of one product entry point (sable_spmv,
+    sable_csr_spmv, sable_spmm, their _f64 forms) with its arguments marshalled once, so that
+    a loop of launches of kernels that take a few microseconds is bound by the GPU rather
+    than by per-call argument conversion. args: tensors (device pointers) and ints (n)."""
+    f = getattr(lib(), fn)
+    cargs = [p.h] + [ctypes.c_int32(a) if isinstance(a, int) else _ptr(a) for a in args]
+    cargs.append(_stream(stream))
+
+    def call():
+        rc = f(*cargs)
+        if rc:
+            _check(fn, rc)
+    return call
+
+
 def sable_update_values(p: Plan, values, stream=None) -> None:
     _check("sable_update_values", lib().sable_update_values(p.h, _ptr(values), _stream(stream)))
 

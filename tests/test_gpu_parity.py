@@ -377,3 +377,21 @@ def test_far_split_absent_below_thresholds():
     p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, oracle.Thresholds())
     assert sable.sable_plan_info(p)["far_split"] == 0
     check_spmv(p, A, synth.gen_dense_vector(2, A.ncols))
+
+
+def test_prebound_launcher_matches_direct_calls():
+    """sable.launcher marshals once and calls the same entry points: identical results."""
+    A, x = synth.gen_c1(6, n=1024)
+    p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, oracle.Thresholds(amin_band=256, amin_block=256))
+    xd = torch.from_numpy(x).cuda()
+    y1, y2 = torch.empty(A.nrows, device="cuda"), torch.empty(A.nrows, device="cuda")
+    sable.sable_spmv(p, xd, y1)
+    sable.launcher("sable_spmv", p, xd, y2)()
+    X = torch.from_numpy(synth.gen_dense_matrix(2, A.ncols, 8)).cuda()
+    Y1, Y2 = torch.empty(A.nrows, 8, device="cuda"), torch.empty(A.nrows, 8, device="cuda")
+    sable.sable_spmm(p, X, Y1, 8)
+    sable.launcher("sable_spmm", p, X, Y2, 8)()
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2) and torch.equal(Y1, Y2)
+    with pytest.raises(sable.SableError):
+        sable.launcher("sable_spmm", p, X, Y2, 0)()  # n < 1 is rejected by the entry point
