@@ -164,6 +164,45 @@ def rocsparse_csrmv_ms(A, ip, ix, vv, xd, y, steps, warmup, torch):
     return ms, y
 
 
+def rocsparse_csrmm_ms(A, ip, ix, vv, Xd, n, steps, warmup, torch):
+    """Reference point: ROCm's CSR SpMM (rocsparse_scsrmm) on the same matrix and row-major X
+    (passed as the transpose of a column-major n x ncols matrix); its output is column-major.
+    Event-timed per launch. Returns (ms, C as an nrows x n view) or (None, None)."""
+    import ctypes
+    try:
+        L = ctypes.CDLL("librocsparse.so")
+    except OSError:
+        return None, None
+    P, i32 = ctypes.c_void_p, ctypes.c_int32
+
+    def ok(rc, fn):
+        if rc != 0:
+            raise RuntimeError(f"{fn} failed: {rc}")
+
+    h, d = P(), P()
+    ok(L.rocsparse_create_handle(ctypes.byref(h)), "create_handle")
+    ok(L.rocsparse_set_stream(h, P(torch.cuda.current_stream().cuda_stream)), "set_stream")
+    ok(L.rocsparse_create_mat_descr(ctypes.byref(d)), "create_mat_descr")
+    C = torch.empty(n, A.nrows, device="cuda")  # column-major nrows x n
+    one, zero = ctypes.c_float(1.0), ctypes.c_float(0.0)
+    cargs = (h, i32(111), i32(112), i32(A.nrows), i32(n), i32(A.ncols), i32(A.nnz),
+             ctypes.byref(one), d, P(vv.data_ptr()), P(ip.data_ptr()), P(ix.data_ptr()),
+             P(Xd.data_ptr()), i32(n), ctypes.byref(zero), P(C.data_ptr()), i32(A.nrows))
+    fn = L.rocsparse_scsrmm
+
+    def f():
+        rc = fn(*cargs)
+        if rc != 0:
+            ok(rc, "scsrmm")
+    try:
+        _, ms = timed_steps(f, steps, warmup, torch)
+    except RuntimeError:
+        ms = None
+    L.rocsparse_destroy_mat_descr(d)
+    L.rocsparse_destroy_handle(h)
+    return ms, (C.t() if ms else None)
+
+
 def cpu_baseline_spmv(A, x, target_s=10.0):
     import oracle
     threads = oracle.max_threads()
@@ -389,11 +428,27 @@ def run_spmm(args, torch, sable, synth):
     log(f"[bench] plan: {info}")
     Xd = torch.from_numpy(X).cuda()
     Y = torch.empty(A.nrows, n, device="cuda")
+    if args.autotune:
+        sable.sable_autotune(p, 1, n, Xd, Y)
     f_h = sable.launcher("sable_spmm", p, Xd, Y, n)
     wall, ev_ms = timed_steps(f_h, args.steps, args.warmup, torch)
     rows = np.random.default_rng(0).choice(A.nrows, 4096, replace=False)
+    rows_d = torch.from_numpy(rows).cuda()
     ref = ref_spmm_rows(A, X, rows)
-    err = rel_err(Y[torch.from_numpy(rows).cuda()].cpu().numpy(), ref)
+    err = rel_err(Y[rows_d].cpu().numpy(), ref)
+    # plain CSR SpMM: the whole input as CSR through the fused SpMM kernel (autotuned)
+    q = sable.plan_host(A, [sable.SABLE_X_CSR], sable.SABLE_VBR_TILED, sable.Thresholds())
+    Yq = torch.empty_like(Y)
+    if args.autotune:
+        sable.sable_autotune(q, 1, n, Xd, Yq)
+    _, ev_q = timed_steps(sable.launcher("sable_spmm", q, Xd, Yq, n), args.steps, args.warmup, torch)
+    err_q = rel_err(Yq[rows_d].cpu().numpy(), ref)
+    del Yq
+    q.destroy()
+    ip_, ix_, vv_ = p._src
+    rs_ms, C = rocsparse_csrmm_ms(A, ip_, ix_, vv_, Xd, n, args.steps, args.warmup, torch)
+    rs_err = rel_err(C[rows_d].cpu().numpy(), ref) if rs_ms else None
+    del C
     ms = wall / args.steps * 1e3
     gflops = 2.0 * A.nnz * n / (ms * 1e-3) / 1e9
     bytes_h = info["bytes_matrix"] + 4 * (A.nrows + A.ncols) * n
@@ -410,7 +465,15 @@ def run_spmm(args, torch, sable, synth):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "launch_ms": round(ev_ms, 4)},
         "rel_err_fp64_sampled": err,
+        "plain_csr": {"launch_ms": round(ev_q, 4),
+                      "gflops": round(2.0 * A.nnz * n / (ev_q * 1e-3) / 1e9, 2),
+                      "rel_err_fp64_sampled": err_q},
+        "speedup_vs_plain_csr": round(ev_q / ev_ms, 4),
+        "rocsparse_csrmm": None if rs_ms is None else {
+            "launch_ms": round(rs_ms, 4), "gflops": round(2.0 * A.nnz * n / (rs_ms * 1e-3) / 1e9, 2),
+            "rel_err_fp64_sampled": rs_err, "speedup_hybrid_vs_rocsparse": round(rs_ms / ev_ms, 4)},
         "partition": {k: info[k] for k in ("nseg", "vdia_nnz", "nblk", "vbr_nnz", "csr_nnz")},
+        "spmm_mode": info["spmm_variant"],
         "plan_ms": round(info["plan_ms"], 1),
     }
     if not args.no_cpu:

@@ -297,6 +297,8 @@ __global__ __launch_bounds__(256) void k_spmv_plain(const int32_t* __restrict__ 
   csr_rows<W>(ptr, col, val, nrows, x, y, blockIdx.x * rows_per_block, rows_per_block);
 }
 
+// Blocks on matrix cores (mfma 1 or 2; the VALU block path is compiled out, so it does not
+// set this kernel's register budget).
 __global__ __launch_bounds__(kMmThreads, 4) void k_spmm_tile(PlanView P, const float* __restrict__ X,
                                                          float* __restrict__ Y, int n, int mfma) {
   __shared__ float ys[kMmRows * kMmCols + kMmBlkStage * kBlkDesc];
@@ -304,7 +306,18 @@ __global__ __launch_bounds__(kMmThreads, 4) void k_spmm_tile(PlanView P, const f
   int t = xcd_tile(blockIdx.x, ntile);
   if (t >= ntile) return;
   if (P.tile_order) t = P.tile_order[t];
-  spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, mfma);
+  spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, mfma == 2 ? 2 : 1);
+}
+
+// Blocks on the VALU in fp32 (the same tile, mfma = 0).
+__global__ __launch_bounds__(kMmThreads, 4) void k_spmm_tile_valu(PlanView P, const float* __restrict__ X,
+                                                              float* __restrict__ Y, int n) {
+  __shared__ float ys[kMmRows * kMmCols + kMmBlkStage * kBlkDesc];
+  const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
+  int t = xcd_tile(blockIdx.x, ntile);
+  if (t >= ntile) return;
+  if (P.tile_order) t = P.tile_order[t];
+  spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, 0);
 }
 
 // FP64 executor: the same streamed SpMV tile body and SpMM tile (blocks on the VALU) over the
@@ -607,7 +620,8 @@ void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStre
     const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
     dim3 grid((unsigned)(((ntile + 7) / 8) * 8), (unsigned)((n + kMmCols - 1) / kMmCols));
     const int mfma = spmm_mfma_mode(P);
-    k_spmm_tile<<<grid, kMmThreads, 0, s>>>(v, X, Y, n, mfma);
+    if (mfma) k_spmm_tile<<<grid, kMmThreads, 0, s>>>(v, X, Y, n, mfma);
+    else k_spmm_tile_valu<<<grid, kMmThreads, 0, s>>>(v, X, Y, n);
   }
   LAUNCH_CHECK();
 }

@@ -169,41 +169,87 @@ __device__ __forceinline__ void mfma_small_batch(const PlanView& P, const int* s
   }
 }
 
-// Blocks on the VALU in the tile's value type: lanes across columns, one row per lane group;
-// block partials are added to the band partials in ys (the tile of Y in LDS).
+// Blocks on the VALU in the tile's value type: lanes across columns, each loaded row of X
+// multiplied into up to 8 block rows; block partials are added to the band partials in ys
+// (the tile of Y in LDS).
+static_assert(kMmRows == 64, "the VALU block path gives each of the 4 waves 16 tile rows");
 template <class T>
 __device__ __forceinline__ void spmm_blocks_valu(const PlanView& P, int* sb, int blo, int bhi, int r0,
                                                  int rend, int cb, int n, const T* __restrict__ X,
                                                  T* __restrict__ ys, int wave, int rpw, int sub,
                                                  int cA, int cB, bool okA, bool okB) {
-    for (int q0 = blo; q0 < bhi; q0 += kMmBlkStage) {
-     const int nq = min(kMmBlkStage, bhi - q0);
-     stage_blocks(P, q0, nq, sb);
-     for (int j = 0; j < nq; ++j) {
+  // Wave w owns tile rows [16 w, 16 w + 16). A block's rows in that range go in chunks of up
+  // to 8 rows per lane group (rows rc + sub + rpw i); each block column k loads one row of X
+  // (two columns per lane) and multiplies it into every row of the chunk, so a loaded row of
+  // X serves all rows of the block; two block columns are in flight together. Per row and
+  // column: block columns ascending, blocks in tile-list order.
+  const int wr0 = r0 + 16 * wave, wr1 = min(r0 + 16 * wave + 16, rend);
+  const int cAc = okA ? cA : 0, cBc = okB ? cB : 0;  // loads stay inside the chunk
+  for (int q0 = blo; q0 < bhi; q0 += kMmBlkStage) {
+    const int nq = min(kMmBlkStage, bhi - q0);
+    stage_blocks(P, q0, nq, sb);  // also orders the band phase's LDS writes before these
+    for (int j = 0; j < nq; ++j) {
       const int* dsc = sb + kBlkDesc * j;
       const int br0 = dsc[0], br1 = dsc[1];
-      const int lo = max(br0, r0), hi = min(br1, rend);
-      if (lo >= hi) continue;
+      const int a = max(br0, wr0), b = min(br1, wr1);
+      if (a >= b) continue;
       const int c0 = dsc[2], c1 = dsc[3];
       const int h = br1 - br0, w = c1 - c0;
       const i64 vp = (i64)(((uint64_t)(uint32_t)dsc[5] << 32) | (uint32_t)dsc[4]);
-      for (int rl = wave * rpw + sub; rl < kMmRows; rl += 4 * rpw) {
-        const int r = r0 + rl;
-        if (r < lo || r >= hi) continue;
-        const T* v = Vals<T>::vbr(P) + vp + (r - br0);
-        T a0 = 0, a1 = 0;
-        for (int k = 0; k < w; ++k) {
-          const T a = v[(i64)k * h];
-          const T* xr = X + (i64)(c0 + k) * n + cb;
-          if (okA) a0 += a * xr[cA];
-          if (okB) a1 += a * xr[cB];
+      const T* vb = Vals<T>::vbr(P) + vp;  // cell (r, c0 + k) at vb[k h + r - br0]
+      for (int rc = a; rc < b; rc += 8 * rpw) {
+        T accA[8], accB[8];
+        int off[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int row = rc + sub + rpw * i;
+          off[i] = (row < b ? row : a) - br0;  // rows past the chunk read a valid cell
+          accA[i] = 0;
+          accB[i] = 0;
         }
-        if (okA) ys[rl * kMmCols + cA] += a0;
-        if (okB) ys[rl * kMmCols + cB] += a1;
+        int k = 0;
+        for (; k + 2 <= w; k += 2) {
+          T xa[2], xb[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const T* xr = X + (i64)(c0 + k + u) * n + cb;
+            xa[u] = xr[cAc];
+            xb[u] = xr[cBc];
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const T* vk = vb + (i64)(k + u) * h;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const T av = vk[off[i]];
+              accA[i] += av * xa[u];
+              accB[i] += av * xb[u];
+            }
+          }
+        }
+        for (; k < w; ++k) {
+          const T* xr = X + (i64)(c0 + k) * n + cb;
+          const T xa = xr[cAc], xb = xr[cBc];
+          const T* vk = vb + (i64)k * h;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const T av = vk[off[i]];
+            accA[i] += av * xa;
+            accB[i] += av * xb;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int row = rc + sub + rpw * i;
+          if (row >= b) continue;
+          T* yr = ys + (row - r0) * kMmCols;
+          if (okA) yr[cA] += accA[i];
+          if (okB) yr[cB] += accB[i];
+        }
       }
-     }
     }
-    __syncthreads();
+  }
+  __syncthreads();
 }
 
 // Rows [r0, r0+kMmRows) x columns [cb, cb+nc) of Y. lds = kMmRows x kMmCols floats for the
