@@ -21,6 +21,17 @@
 
 namespace sable {
 
+// Lane l's value of v, for every lane (l wave-uniform).
+__device__ __forceinline__ float readlane_val(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane_val(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 constexpr int kMmRows = 64;
 constexpr int kMmCols = 128;
 constexpr int kMmThreads = 256;
@@ -420,31 +431,70 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
     // eight X rows in flight per lane: indices and values first, then every X load
     // (columns clamped into the chunk, masked when used)
     const int cAc = min(cA, nc - 1), cBc = min(cB, nc - 1);
-    for (; k + 8 <= ke; k += 8) {
-      int cc[8];
-      T va[8], xa[8], xb[8];
+    if (rpw == 1) {
+      // the whole wave is on this row: its entries are loaded 64 at a time, one per lane,
+      // and handed to every lane with readlane (two index loads per 64 entries instead of
+      // two per entry); the products are added in index order as below
+      for (; k < ke; k += 64) {
+        const int cnt = min(64, ke - k);
+        const int kl = k + min(lane, cnt - 1);
+        const int mc = __builtin_nontemporal_load(P.csr_col + kl);
+        const T mv = __builtin_nontemporal_load(Vals<T>::csr(P) + kl);
+        int u = 0;
+        for (; u + 4 <= cnt; u += 4) {
+          int cc[4];
+          T va[4], xa[4], xb[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        cc[u] = __builtin_nontemporal_load(P.csr_col + k + u);
-        va[u] = __builtin_nontemporal_load(Vals<T>::csr(P) + k + u);
-      }
+          for (int j = 0; j < 4; ++j) {
+            cc[j] = __builtin_amdgcn_readlane(mc, u + j);
+            va[j] = readlane_val(mv, u + j);
+          }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const T* xr = X + (i64)cc[u] * n + cb;
-        xa[u] = xr[cAc];
-        xb[u] = xr[cBc];
-      }
+          for (int j = 0; j < 4; ++j) {
+            const T* xr = X + (i64)cc[j] * n + cb;
+            xa[j] = xr[cAc];
+            xb[j] = xr[cBc];
+          }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        a0 += va[u] * (okA ? xa[u] : T(0));
-        a1 += va[u] * (okB ? xb[u] : T(0));
+          for (int j = 0; j < 4; ++j) {
+            a0 += va[j] * (okA ? xa[j] : T(0));
+            a1 += va[j] * (okB ? xb[j] : T(0));
+          }
+        }
+        for (; u < cnt; ++u) {
+          const T v0 = readlane_val(mv, u);
+          const T* x0 = X + (i64)__builtin_amdgcn_readlane(mc, u) * n + cb;
+          if (okA) a0 += v0 * x0[cA];
+          if (okB) a1 += v0 * x0[cB];
+        }
       }
-    }
-    for (; k < ke; ++k) {
-      const T v0 = Vals<T>::csr(P)[k];
-      const T* x0 = X + (i64)P.csr_col[k] * n + cb;
-      if (okA) a0 += v0 * x0[cA];
-      if (okB) a1 += v0 * x0[cB];
+    } else {
+      for (; k + 8 <= ke; k += 8) {
+        int cc[8];
+        T va[8], xa[8], xb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          cc[u] = __builtin_nontemporal_load(P.csr_col + k + u);
+          va[u] = __builtin_nontemporal_load(Vals<T>::csr(P) + k + u);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const T* xr = X + (i64)cc[u] * n + cb;
+          xa[u] = xr[cAc];
+          xb[u] = xr[cBc];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a0 += va[u] * (okA ? xa[u] : T(0));
+          a1 += va[u] * (okB ? xb[u] : T(0));
+        }
+      }
+      for (; k < ke; ++k) {
+        const T v0 = Vals<T>::csr(P)[k];
+        const T* x0 = X + (i64)P.csr_col[k] * n + cb;
+        if (okA) a0 += v0 * x0[cA];
+        if (okB) a1 += v0 * x0[cB];
+      }
     }
     T* yr = Y + (i64)r * n + cb;
     // Y is written once: non-temporal stores keep it from evicting X
