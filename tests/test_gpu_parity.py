@@ -251,6 +251,35 @@ def test_every_spmv_variant_and_baseline():
         assert oracle.rel_err(y.cpu().numpy(), ref) <= 1e-5, v
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (5, 300), (300, 5), (17, 17), (257, 129)])
+def test_every_variant_on_tiny_and_ragged_shapes(shape):
+    """Every SpMV variant, plain CSR variant and SpMM mode on shapes smaller than or ragged
+    against every tile height (256 RPT rows, 256 / W rows, 64-row SpMM tiles)."""
+    nr, nc = shape
+    A = synth.gen_random_small(7 * nr + nc, nr, nc, 0.3, nbands=1, nblocks=1)
+    th = oracle.Thresholds(lseg=2, amin_band=2, amin_block=4)
+    x = synth.gen_dense_vector(2, nc)
+    ref = oracle.spmv(A, x)
+    p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
+    xd = torch.from_numpy(x).cuda()
+    y = torch.empty(nr, device="cuda")
+    for v in range(11):
+        sable.sable_plan_set_variant(p, 0, v)
+        check_spmv(p, A, x)
+    for v in range(13):
+        sable.sable_plan_set_variant(p, 2, v)
+        sable.sable_csr_spmv(p, xd, y)
+        torch.cuda.synchronize()
+        assert oracle.rel_err(y.cpu().numpy(), ref) <= 1e-5, v
+    X = synth.gen_dense_matrix(3, nc, 5)
+    for m in range(4):
+        sable.sable_plan_set_variant(p, 1, m)
+        Y = torch.full((nr, 5), float("nan"), device="cuda")
+        sable.sable_spmm(p, torch.from_numpy(X).cuda(), Y, 5)
+        torch.cuda.synchronize()
+        assert oracle.rel_err(Y.cpu().numpy(), oracle.spmm(A, X)) <= 1e-4, m
+
+
 @pytest.mark.parametrize("n", [1, 3, 16, 64, 128, 130, 200])
 def test_spmm_modes_and_widths(n):
     A, _ = synth.gen_c1(4, n=1536)
