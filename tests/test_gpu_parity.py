@@ -345,6 +345,29 @@ def test_c2_full_size_sampled(seed):
     assert err <= 1e-5
 
 
+def test_c3_full_size_sampled():
+    """FEM-like 500,000-row matrix, SpMM with n = 128, in the benchmark's configuration
+    (autotuned, blocks on matrix cores as split bf16): exact cover of every input entry, and
+    sampled rows (plus the first and last) against the FP64 oracle."""
+    A, X = synth.gen_c3(0)
+    th = oracle.Thresholds(delta_band_pm=900, delta_block_pm=900, amin_block=36)
+    p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
+    n = X.shape[1]
+    Xd = torch.from_numpy(X).cuda()
+    Y = torch.empty(A.nrows, n, device="cuda")
+    sable.sable_autotune(p, 1, n, Xd, Y)
+    oracle.check_partition(A, sable.sable_plan_export(p), th, [V, B, C])
+    Y.fill_(float("nan"))
+    sable.sable_spmm(p, Xd, Y, n)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(3).choice(A.nrows, 2048, replace=False)
+    rows = np.concatenate([rows, [0, A.nrows - 1]])
+    got = Y[torch.from_numpy(rows).cuda()].cpu().numpy()
+    err = oracle.rel_err(got, oracle.spmm_rows(A, X, rows))
+    print(f"  sampled rel_err={err:.3e} (spmm mode {sable.sable_plan_info(p)['spmm_variant']})")
+    assert err <= 1e-4
+
+
 # ---- far-column split of the CSR part (streamed SpMV) ------------------------------------
 
 FAR_WINDOW = 1 << 17  # entries more than this many columns from their row are far
