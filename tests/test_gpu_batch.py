@@ -97,3 +97,48 @@ def test_batch_rejects_bad_items():
     bad = [(0, 2, items[0][2], items[0][3])] + items[1:]
     with pytest.raises(sable.SableError):
         sable.sable_batch_create(plans, bad)
+
+
+def test_serving_batch_full_size():
+    """The benchmark's serving batch: 256 generated matrices (1e3 - 2e5 rows, SpMV or SpMM
+    with 16 right-hand sides), planner-chosen plans; every item bitwise equal to its
+    standalone launch, and sampled items against the FP64 oracle."""
+    import concurrent.futures as cf
+
+    import oracle
+    from paper_2407_00829_amd import planner
+    params, mean, std, tau = planner.load_weights(planner.WEIGHTS)
+    Pd = torch.from_numpy(params).cuda()
+    with cf.ProcessPoolExecutor(8) as ex:
+        mats = list(ex.map(synth.gen_c5_matrix, range(256)))
+    plans, items = [], []
+    for i, (A, kind, op) in enumerate(mats):
+        ip, ix, vv = sable.device_csr(A)
+        x = torch.from_numpy(synth.gen_dense_vector(i, A.ncols)).cuda()
+        y = torch.empty(A.nrows, device="cuda")
+        p, _, _, _ = sable.sable_plan_auto(A.nrows, A.ncols, ip, ix, vv, Pd, mean, std, tau, x, y)
+        p._src = (ip, ix, vv)
+        if op == 0:
+            items.append((0, 1, x, torch.full((A.nrows,), float("nan"), device="cuda")))
+        else:
+            X = torch.from_numpy(synth.gen_dense_matrix(i, A.ncols, 16)).cuda()
+            items.append((1, 16, X, torch.full((A.nrows, 16), float("nan"), device="cuda")))
+        plans.append(p)
+    print(f"[batch] {len(plans)} plans", flush=True)
+    ref = standalone(plans, items)
+    b = sable.sable_batch_create(plans, items)
+    sable.sable_batch_run(b)
+    torch.cuda.synchronize()
+    for i, ((_, _, _, y), r) in enumerate(zip(items, ref)):
+        assert torch.equal(y, r), i
+    for i in range(0, 256, 32):
+        A, _, op = mats[i]
+        _, n, x, y = items[i]
+        if op == 0:
+            err = oracle.rel_err(y.cpu().numpy(), oracle.spmv(A, x.cpu().numpy()))
+            assert err <= 1e-5, (i, err)
+        else:
+            rows = np.arange(min(A.nrows, 4096))
+            err = oracle.rel_err(y.cpu().numpy()[rows], oracle.spmm_rows(A, x.cpu().numpy(), rows))
+            assert err <= 1e-4, (i, err)
+    b.destroy()
