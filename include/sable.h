@@ -224,8 +224,9 @@ sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, const float* 
                             void* stream);
 
 /* Select a fused-kernel variant explicitly (the set sable_autotune chooses from).
- * op 0 = hybrid SpMV: 0..2 streamed tiles of 256/512/1024 rows, 3..7 row-per-lane with
- *        1/2/4/8/16 lanes per CSR row, 8..10 = 0..2 with non-temporal matrix loads,
+ * op 0 = hybrid SpMV: 0..2 streamed tiles of 256/512/1024 rows, 3..7 with 1/2/4/8/16 lanes
+ *        per row on tiles of 256/W rows (bands lane per row; for W > 1 a row's lanes share its
+ *        block columns and CSR entries), 8..10 = 0..2 with non-temporal matrix loads,
  *        11 = the run-time specialized kernel (after sable_plan_specialize);
  * op 1 = SpMM: 0 tiled with matrix-core blocks (for n <= 32 the four waves split the tile's
  *        row slices, otherwise its column chunks), 1 tiled fp32, 2 one wave per row, 3 tiled
