@@ -79,7 +79,8 @@ def pmc_summary(argv):
     ap = argparse.ArgumentParser(prog="profsum pmc")
     ap.add_argument("--name", required=True)
     ap.add_argument("--kernel", required=True)
-    ap.add_argument("--dir", required=True)
+    ap.add_argument("--dir", required=True, action="append",
+                    help="counter output directory (repeat for several counter passes)")
     ap.add_argument("--trace", required=True)
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--trace-cmd", required=True)
@@ -89,18 +90,22 @@ def pmc_summary(argv):
                     help="algorithmic FLOP of one dispatch (2 nnz n x 3 products)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args(argv)
-    rows = [r for r in _csv(a.dir, "counter_collection.csv") if a.kernel in r["Kernel_Name"]]
-    if not rows:
-        raise ValueError(f"kernel {a.kernel!r} not found under {a.dir}")
-    by = {}
-    for r in rows:
-        by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    by, passes = {}, []
+    for d in a.dir:
+        rows = [r for r in _csv(d, "counter_collection.csv") if a.kernel in r["Kernel_Name"]]
+        if not rows:
+            raise ValueError(f"kernel {a.kernel!r} not found under {d}")
+        names = sorted({r["Counter_Name"] for r in rows})
+        passes.append(names)
+        for r in rows:
+            by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     mean = {k: sum(v) / len(v) for k, v in by.items()}
     st = [r for r in kernel_stats(a.trace) if a.kernel in r["Name"]]
     avg_us = float(st[0]["AverageNs"]) / 1e3 if st else 0.0
     md = [f"# {a.name}: rocprofv3 counters of `{a.kernel}`", "",
           "Commands (run from /tmp with TMPDIR=/tmp; DIR is an output directory):", "",
-          f"    rocprofv3 --pmc {' '.join(sorted(mean))} --output-format csv -d DIR -o run -- {a.cmd}",
+          *[f"    rocprofv3 --pmc {' '.join(p)} --output-format csv -d DIR -o run -- {a.cmd}"
+            for p in passes],
           f"    rocprofv3 --kernel-trace --stats --output-format csv -d DIR -o run -- {a.trace_cmd}", "",
           "| counter | mean per dispatch |", "|---|---|"]
     for k in sorted(mean):
@@ -108,6 +113,15 @@ def pmc_summary(argv):
     md.append("")
     if st:
         md.append(f"* Kernel-trace average duration: {avg_us:.1f} us over {st[0]['Calls']} dispatches.")
+    if "SQ_WAIT_ANY" in mean and "SQ_WAVE_CYCLES" in mean:
+        md.append(f"* Waves waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES): "
+                  f"{100 * mean['SQ_WAIT_ANY'] / mean['SQ_WAVE_CYCLES']:.1f}% of their cycles.")
+    if mean.get("SQ_ACTIVE_INST_VMEM") and "SQ_WAVE_CYCLES" in mean:  # 0 where not counted
+        md.append(f"* Issuing vector memory instructions (SQ_ACTIVE_INST_VMEM / SQ_WAVE_CYCLES): "
+                  f"{100 * mean['SQ_ACTIVE_INST_VMEM'] / mean['SQ_WAVE_CYCLES']:.1f}%.")
+    if "TCC_HIT_sum" in mean and "TCC_MISS_sum" in mean:
+        h, m = mean["TCC_HIT_sum"], mean["TCC_MISS_sum"]
+        md.append(f"* L2 hit rate (TCC_HIT / (TCC_HIT + TCC_MISS)): {100 * h / max(h + m, 1):.1f}%.")
     if "SQ_VALU_MFMA_BUSY_CYCLES" in mean and "GRBM_GUI_ACTIVE" in mean:
         gui = mean["GRBM_GUI_ACTIVE"] / a.xcds  # one XCD's active cycles
         util = mean["SQ_VALU_MFMA_BUSY_CYCLES"] / (gui * a.simds)
