@@ -201,6 +201,8 @@ sable_status sable_csr_spmv(sable_plan_t p, const float* x, float* y, void* stre
  * tile bodies in fp64 (VBR blocks on the fp64 VALU: gfx950's fp64 matrix-core peak equals
  * its fp64 vector peak); x[ncols], y[nrows], X[ncols x n], Y[nrows x n] device fp64,
  * row-major. Summation orders are fixed as in the fp32 executor (bitwise reproducible).
+ * The far-column split (op 3 of sable_plan_set_variant) applies to sable_spmv_f64 as well,
+ * with fp64 copies of the far entries' values and products (the same result bit for bit).
  * Both return SABLE_ERR_INVALID_ARG until fp64 values have been set. */
 sable_status sable_update_values_f64(sable_plan_t p, const double* values, void* stream);
 sable_status sable_spmv_f64(sable_plan_t p, const double* x, double* y, void* stream);

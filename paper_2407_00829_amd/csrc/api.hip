@@ -181,7 +181,7 @@ sable::i64 sable_plan_s::device_bytes() const {
          S->tile_blk.bytes() + S->order.bytes() + S->row0.bytes();
   }
   b += far.ccol.bytes() + far.far_col.bytes() + far.far_src.bytes() + far.far_val.bytes() +
-       far.far_prod.bytes() + far.chunk.bytes();
+       far.far_prod.bytes() + far.far_val64.bytes() + far.far_prod64.bytes() + far.chunk.bytes();
   return b;
 }
 
@@ -386,6 +386,7 @@ sable_status sable_update_values_f64(sable_plan_t p, const double* values, void*
           nullptr);
       LAUNCH_CHECK();
     }
+    refresh_far_values64(*p, s);
     p->has_f64 = true;
   });
 }

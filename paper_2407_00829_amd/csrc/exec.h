@@ -38,6 +38,7 @@ struct PlanView {
   // far-column split: when far_prod is set, csr_col holds negative codes -(1 + q) for entries
   // whose product far_prod[q] the gather pass has already computed
   const float* far_prod;
+  const double* far_prod64;  // the same for the fp64 executor
 };
 
 // Value arrays of the view for the executor's value type.
@@ -48,12 +49,14 @@ struct Vals<float> {
   __device__ static const float* vdia(const PlanView& P) { return P.vdia_val; }
   __device__ static const float* vbr(const PlanView& P) { return P.vbr_val; }
   __device__ static const float* csr(const PlanView& P) { return P.csr_val; }
+  __device__ static const float* far(const PlanView& P) { return P.far_prod; }
 };
 template <>
 struct Vals<double> {
   __device__ static const double* vdia(const PlanView& P) { return P.vdia_val64; }
   __device__ static const double* vbr(const PlanView& P) { return P.vbr_val64; }
   __device__ static const double* csr(const PlanView& P) { return P.csr_val64; }
+  __device__ static const double* far(const PlanView& P) { return P.far_prod64; }
 };
 
 // far = true: the view with the far-column split, if the plan has one and it is enabled.
@@ -212,14 +215,9 @@ __device__ __forceinline__ void csr_issue(const PlanView& P, int e0, int e_end,
     f.j[u] = ld<NT>(P.csr_col + k);
     f.a[u] = ld<NT>(val + k);
   }
-  if constexpr (sizeof(T) == 4) {  // far-column products exist for fp32 only
-    const float* fp = P.far_prod ? P.far_prod : x;
+  const T* fp = Vals<T>::far(P) ? Vals<T>::far(P) : x;  // stored far-column products
 #pragma unroll
-    for (int u = 0; u < U; ++u) f.v[u] = *(f.j[u] >= 0 ? x + f.j[u] : fp + (-1 - f.j[u]));
-  } else {
-#pragma unroll
-    for (int u = 0; u < U; ++u) f.v[u] = x[f.j[u]];
-  }
+  for (int u = 0; u < U; ++u) f.v[u] = *(f.j[u] >= 0 ? x + f.j[u] : fp + (-1 - f.j[u]));
 }
 
 template <class T, int U>

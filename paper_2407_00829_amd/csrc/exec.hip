@@ -51,6 +51,7 @@ PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool fa
   if (far && P.far.npanel && P.prm.far_split) {
     v.csr_col = P.far.ccol.p;
     v.far_prod = P.far.far_prod.p;
+    v.far_prod64 = P.far.far_prod64.p;
   }
   return v;
 }
@@ -222,13 +223,14 @@ __global__ __launch_bounds__(256) void k_spmv_stream(PlanView P, const float* __
 // Far-column gather: workgroup b runs on XCD b mod 8 and takes that XCD's (b / 8)-th work
 // item (begin, end, panel); it stages the panel's x slice in LDS with coalesced loads, then
 // multiplies its entries by x values read from LDS.
+template <class T>
 __global__ __launch_bounds__(kFarThreads) void k_far_gather(const int32_t* __restrict__ chunk,
                                                            int per_xcd, int ncols,
                                                            const uint16_t* __restrict__ col,
-                                                           const float* __restrict__ val,
-                                                           const float* __restrict__ x,
-                                                           float* __restrict__ prod) {
-  __shared__ float xs[kFarPanelCols];
+                                                           const T* __restrict__ val,
+                                                           const T* __restrict__ x,
+                                                           T* __restrict__ prod) {
+  __shared__ T xs[kFarPanelCols];  // fp32: 32 KB, fp64: 64 KB
   const int* c = chunk + 3 * ((blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3));
   const int b = c[0], e = c[1], panel = c[2];
   if (b < 0) return;
@@ -237,29 +239,34 @@ __global__ __launch_bounds__(kFarThreads) void k_far_gather(const int32_t* __res
   const int w = min(kFarPanelCols, ncols - base);
   // this thread's entries first (independent of the slice), then the slice
   int j[8];
-  float a[8];
+  T a[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int k = b + t + kFarThreads * u;
     j[u] = k < e ? (int)__builtin_nontemporal_load(col + k) : 0;
-    a[u] = k < e ? __builtin_nontemporal_load(val + k) : 0.f;
+    a[u] = k < e ? __builtin_nontemporal_load(val + k) : T(0);
   }
-  // slice: all loads of a thread in flight together (float4 when x is 16-byte aligned)
-  constexpr int kV = kFarPanelCols / (4 * kFarThreads);  // float4 per thread
-  if (((uintptr_t)x & 15) == 0 && w == kFarPanelCols) {
-    float4 v[kV];
-    const float4* x4 = reinterpret_cast<const float4*>(x + base);
+  // slice: all loads of a thread in flight together (fp32: float4 when x is 16-byte aligned)
+  bool vec = false;
+  if constexpr (sizeof(T) == 4) {
+    vec = ((uintptr_t)x & 15) == 0 && w == kFarPanelCols;
+    if (vec) {
+      constexpr int kV = kFarPanelCols / (4 * kFarThreads);  // float4 per thread
+      float4 v[kV];
+      const float4* x4 = reinterpret_cast<const float4*>(x + base);
 #pragma unroll
-    for (int u = 0; u < kV; ++u) v[u] = x4[t + kFarThreads * u];
+      for (int u = 0; u < kV; ++u) v[u] = x4[t + kFarThreads * u];
 #pragma unroll
-    for (int u = 0; u < kV; ++u) reinterpret_cast<float4*>(xs)[t + kFarThreads * u] = v[u];
-  } else {
+      for (int u = 0; u < kV; ++u) reinterpret_cast<float4*>(xs)[t + kFarThreads * u] = v[u];
+    }
+  }
+  if (!vec) {
     for (int i0 = 0; i0 < w; i0 += 8 * kFarThreads) {
-      float v[8];
+      T v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int i = i0 + t + kFarThreads * u;
-        v[u] = i < w ? x[base + i] : 0.f;
+        v[u] = i < w ? x[base + i] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -562,7 +569,7 @@ void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s)
     const int k = var <= 2 ? var : var - 8;
     const PlanView v = make_view(P, P.sched[k], false, true);
     if (v.far_prod) {
-      k_far_gather<<<(unsigned)(8 * P.far.per_xcd), kFarThreads, 0, s>>>(
+      k_far_gather<float><<<(unsigned)(8 * P.far.per_xcd), kFarThreads, 0, s>>>(
           P.far.chunk.p, P.far.per_xcd, P.ncols, P.far.far_col.p, P.far.far_val.p, x,
           P.far.far_prod.p);
       LAUNCH_CHECK();
@@ -630,7 +637,13 @@ void launch_spmv_f64(const sable_plan_s& P, const double* x, double* y, hipStrea
   // the streamed variant's tile size (rows per thread) if one is selected, else 1
   const int var = P.prm.spmv_variant;
   const int k = var <= 2 ? var : var >= 8 ? var - 8 : 0;
-  const PlanView v = make_view(P, P.sched[k], false);
+  const PlanView v = make_view(P, P.sched[k], false, P.far.far_prod64.p != nullptr);
+  if (v.far_prod64) {  // far-column products first, as in the fp32 path
+    k_far_gather<double><<<(unsigned)(8 * P.far.per_xcd), kFarThreads, 0, s>>>(
+        P.far.chunk.p, P.far.per_xcd, P.ncols, P.far.far_col.p, P.far.far_val64.p, x,
+        P.far.far_prod64.p);
+    LAUNCH_CHECK();
+  }
   const unsigned nb = (unsigned)(((v.ntiles + 7) / 8) * 8);
   switch (k) {
     case 0: k_spmv_stream_f64<1><<<nb, kSpmvThreads, 0, s>>>(v, x, y); break;

@@ -65,8 +65,9 @@ __global__ void k_panel_ptr(const uint64_t* __restrict__ keys, i64 n, int npanel
   pp[p] = (int32_t)l;
 }
 
-__global__ void k_gather_vals(const float* __restrict__ src, const int32_t* __restrict__ idx, i64 n,
-                              float* __restrict__ out) {
+template <class T>
+__global__ void k_gather_vals(const T* __restrict__ src, const int32_t* __restrict__ idx, i64 n,
+                              T* __restrict__ out) {
   for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
     out[i] = src[idx[i]];
 }
@@ -131,10 +132,22 @@ void build_far_split(sable_plan_s& P, hipStream_t s) {
   HIPC(hipStreamSynchronize(s));
 }
 
+void refresh_far_values64(sable_plan_s& P, hipStream_t s) {
+  FarSplit& F = P.far;
+  if (!F.npanel) return;
+  if (!F.far_val64.p) {
+    F.far_val64.alloc(F.nfar);
+    F.far_prod64.alloc(F.nfar);
+  }
+  k_gather_vals<double><<<grid_for(F.nfar, 256), 256, 0, s>>>(P.csr_val64.p, F.far_src.p, F.nfar,
+                                                              F.far_val64.p);
+  LAUNCH_CHECK();
+}
+
 void refresh_far_values(sable_plan_s& P, hipStream_t s) {
   FarSplit& F = P.far;
   if (!F.npanel) return;
-  k_gather_vals<<<grid_for(F.nfar, 256), 256, 0, s>>>(P.csr_val.p, F.far_src.p, F.nfar, F.far_val.p);
+  k_gather_vals<float><<<grid_for(F.nfar, 256), 256, 0, s>>>(P.csr_val.p, F.far_src.p, F.nfar, F.far_val.p);
   LAUNCH_CHECK();
 }
 

@@ -63,6 +63,7 @@ struct FarSplit {
   DBuf<uint16_t> far_col;             // column within its panel; panel-major, row order inside
   DBuf<int32_t> far_src;              // CSR index of each far entry
   DBuf<float> far_val, far_prod;
+  DBuf<double> far_val64, far_prod64;  // fp64 executor (after fp64 values are set)
   DBuf<int32_t> chunk;  // [8][per_xcd] (begin, end) entry ranges, begin < 0 = none
 };
 
@@ -158,6 +159,8 @@ void build_schedule(sable_plan_s& P, Schedule& S, int rows_per_tile, bool with_f
 void build_bf16_split(sable_plan_s& P, hipStream_t s);
 void build_far_split(sable_plan_s& P, hipStream_t s);
 void refresh_far_values(sable_plan_s& P, hipStream_t s);
+// fp64 copies of the far entries' values (from csr_val64), allocated on first use.
+void refresh_far_values64(sable_plan_s& P, hipStream_t s);
 void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s);

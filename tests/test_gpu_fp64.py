@@ -141,3 +141,43 @@ def test_c2_full_size_fp64_sampled():
     err = oracle.rel_err(y.cpu().numpy()[rows], ref)
     print(f"  sampled rel_err={err:.3e}")
     assert err <= TOL
+
+
+def wide_scatter(nr, nc, seed):
+    """Main diagonal plus ~0.15 uniform-random entries per row and 70,000 more: a CSR part
+    with well over 2^16 entries more than 2^17 columns from their row."""
+    rng = np.random.default_rng(seed)
+    d = np.arange(min(nr, nc))
+    ns = int(0.15 * nr) + 70000
+    rows = np.concatenate([d, rng.integers(0, nr, ns)])
+    cols = np.concatenate([d, rng.integers(0, nc, ns)])
+    vals = rng.uniform(-1, 1, rows.size).astype(np.float32)
+    return synth.from_coo(nr, nc, rows, cols, vals)
+
+
+@pytest.mark.parametrize("shape", [(1_300_001, 1_300_001), (200_003, 3_000_000)])
+def test_far_column_split_fp64(shape):
+    """FP64 executor with the far-column split: every streamed variant matches the oracle
+    with the split on and off, the two agree bit for bit, and a second value update reaches
+    the far entries' fp64 copies."""
+    A = wide_scatter(*shape, seed=shape[0] % 89)
+    p, v = plan64(A, [V, B, C], sable.SABLE_VBR_TILED, sable.Thresholds(), 21)
+    assert sable.sable_plan_info(p)["far_split"] == 1
+    for var in (0, 1, 2):
+        sable.sable_plan_set_variant(p, 0, var)
+        ys = []
+        for fs in (1, 0):
+            sable.sable_plan_set_variant(p, 3, fs)
+            x = np.random.default_rng(22).standard_normal(A.ncols)
+            y = torch.full((A.nrows,), float("nan"), dtype=torch.float64, device="cuda")
+            sable.sable_spmv_f64(p, torch.from_numpy(x).cuda(), y)
+            torch.cuda.synchronize()
+            err = oracle.rel_err(y.cpu().numpy(), oracle.spmv64(A, v, x))
+            print(f"  variant {var} far_split {fs}: rel_err={err:.3e}", flush=True)
+            assert err <= TOL
+            ys.append(y)
+        assert torch.equal(ys[0].view(torch.int64), ys[1].view(torch.int64)), var
+    sable.sable_plan_set_variant(p, 3, 1)
+    v2 = fp64_values(A, 23)
+    sable.sable_update_values_f64(p, torch.from_numpy(v2).cuda())
+    check_spmv64(p, A, v2, 24)
