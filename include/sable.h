@@ -220,8 +220,9 @@ sable_status sable_update_values(sable_plan_t p, const float* values, void* stre
 
 /* ---- Autotuning ---------------------------------------------------------------------
  * Time a small grid of launch parameters for the plan's fused kernel on `stream` (op 0 =
- * SpMV, 1 = SpMM with n columns) and keep the fastest. x/X, y/Y are scratch operands of
- * the right sizes. Synchronises `stream`. */
+ * SpMV, 1 = SpMM with n columns) and keep the fastest. The SpMM choice is kept per n: later
+ * sable_spmm calls with that n use it, other n use the most recent choice. x/X, y/Y are
+ * scratch operands of the right sizes. Synchronises `stream`. */
 sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, const float* x, float* y,
                             void* stream);
 
@@ -236,7 +237,8 @@ sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, const float* 
  * op 2 = plain CSR baseline: 0..2 streamed, 3..9 with 1..64 lanes per row, 10..12 = 0..2
  *        with non-temporal matrix loads;
  * op 3 = far-column split of the streamed SpMV variants: 0 off, 1 on (when the plan has one).
- * Every variant computes the same product; each is bitwise reproducible on its own. */
+ * Every variant computes the same product; each is bitwise reproducible on its own. An
+ * explicit SpMM variant applies to every n (it clears the per-n autotuned choices). */
 sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32_t variant);
 
 /* ---- Run-time specialization (Sec. 3.3 - 3.4 code generation, on the GPU) ------------

@@ -180,7 +180,7 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
           hv[i] = make_view(P, P.sched_mm, false);
           d.units_per_col = (P.nrows + kMmRows - 1) / kMmRows;
           d.col_chunks = (it.n + kMmCols - 1) / kMmCols;
-          d.mfma = spmm_mfma_mode(P);
+          d.mfma = spmm_mfma_mode(P, P.prm.spmm_mode_for(it.n));
           units = (i64)d.units_per_col * d.col_chunks;
         }
       }

@@ -612,21 +612,21 @@ void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStrea
   LAUNCH_CHECK();
 }
 
-int spmm_mfma_mode(const sable_plan_s& P) {
+int spmm_mfma_mode(const sable_plan_s& P, int mode) {
   if (!P.vbr_mma.p || P.nblk == 0) return 0;
-  return P.prm.spmm_mode == 0 ? 1 : P.prm.spmm_mode == 3 ? 2 : 0;
+  return mode == 0 ? 1 : mode == 3 ? 2 : 0;
 }
 
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s) {
-  const PlanView v = make_view(P, P.prm.spmm_mode == 2 ? P.sched[0] : P.sched_mm, false);
-  const int mode = P.prm.spmm_mode;
+  const int mode = P.prm.spmm_mode_for(n);
+  const PlanView v = make_view(P, mode == 2 ? P.sched[0] : P.sched_mm, false);
   if (mode == 2) {
     const unsigned nb = (unsigned)((P.nrows + 3) / 4);
     k_spmm_fused_valu<<<nb, 256, 0, s>>>(v, X, Y, n);
   } else {
     const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
     dim3 grid((unsigned)(((ntile + 7) / 8) * 8), (unsigned)((n + kMmCols - 1) / kMmCols));
-    const int mfma = spmm_mfma_mode(P);
+    const int mfma = spmm_mfma_mode(P, mode);
     if (mfma) k_spmm_tile<<<grid, kMmThreads, 0, s>>>(v, X, Y, n, mfma);
     else k_spmm_tile_valu<<<grid, kMmThreads, 0, s>>>(v, X, Y, n);
   }

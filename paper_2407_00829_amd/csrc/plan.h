@@ -1,6 +1,9 @@
 // Internal plan representation: formats in HBM plus the execution schedule.
 #pragma once
 
+#include <utility>
+#include <vector>
+
 #include "common.h"
 
 namespace sable {
@@ -26,7 +29,7 @@ struct BlkRec {  // block rectangle rows [r0, r1), columns [c0, c1)
 // Launch parameters of the fused kernels (autotuned).
 // SpMV kernel variants: 0..2 = streamed tile body with 1, 2, 4 rows per thread (tiles of
 // 256, 512, 1024 rows); 3..7 = row-per-lane bands/blocks with 1, 2, 4, 8, 16 lanes per CSR
-// row (tiles of 256 rows); 8..10 = 0..2 with non-temporal matrix loads. The plain CSR
+// row (tiles of 256 / W rows); 8..10 = 0..2 with non-temporal matrix loads. The plain CSR
 // baseline: 0..2 streamed, 3..9 = 1..64 lanes per row, 10..12 = 0..2 non-temporal.
 struct ExecParams {
   int spmv_variant = 1;
@@ -34,6 +37,14 @@ struct ExecParams {
   int spmm_mode = 0;  // fused SpMM variant: 0 tiled, matrix cores (automatic work split),
                       // 1 tiled fp32 VALU, 2 wave per row, 3 tiled, matrix cores (chunk split)
   int far_split = 1;  // streamed SpMV: gather far-column CSR entries in a separate pass
+  // SpMM variant the autotuner chose for each number of right-hand sides it was run with;
+  // an explicit sable_plan_set_variant for SpMM clears it
+  std::vector<std::pair<int, int>> spmm_tuned;  // (n, mode)
+  int spmm_mode_for(int n) const {
+    for (const auto& t : spmm_tuned)
+      if (t.first == n) return t.second;
+    return spmm_mode;
+  }
 };
 
 // Far-column split of the CSR remainder (streamed SpMV variants). An entry whose column lies
@@ -165,7 +176,7 @@ void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s)
 void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s);
 // Matrix-core mode of the tiled SpMM for the plan's variant (0 none, 1 auto split, 2 chunks).
-int spmm_mfma_mode(const sable_plan_s& P);
+int spmm_mfma_mode(const sable_plan_s& P, int mode);
 void launch_spmv_f64(const sable_plan_s& P, const double* x, double* y, hipStream_t s);
 void launch_spmv_spec(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmm_f64(const sable_plan_s& P, const double* X, double* Y, int n, hipStream_t s);

@@ -78,13 +78,18 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
     }
     P.prm.plain_variant = pick(tp);
   } else {
-    // x / y hold X (ncols x n) and Y (nrows x n)
+    // x / y hold X (ncols x n) and Y (nrows x n); the choice is kept per n
     std::vector<float> t(4);
+    auto& tuned = P.prm.spmm_tuned;
+    tuned.erase(std::remove_if(tuned.begin(), tuned.end(),
+                               [&](const std::pair<int, int>& e) { return e.first == n; }),
+                tuned.end());
     for (int m = 0; m <= 3; ++m) {
       P.prm.spmm_mode = m;
       t[m] = time_ms([&] { launch_spmm(P, x, y, n, s); }, s, 2);
     }
     P.prm.spmm_mode = pick(t);
+    tuned.push_back({n, P.prm.spmm_mode});
   }
   HIPC(hipStreamSynchronize(s));
 }
@@ -125,7 +130,10 @@ extern "C" sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32
     return SABLE_ERR_INVALID_ARG;
   }
   if (op == 0) p->prm.spmv_variant = variant;
-  else if (op == 1) p->prm.spmm_mode = variant;
+  else if (op == 1) {
+    p->prm.spmm_mode = variant;
+    p->prm.spmm_tuned.clear();
+  }
   else if (op == 2) p->prm.plain_variant = variant;
   else p->prm.far_split = variant;
   return SABLE_OK;

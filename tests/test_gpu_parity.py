@@ -290,6 +290,36 @@ def test_spmm_modes_and_widths(n):
         check_spmm(p, A, n, seed=n)
 
 
+def test_spmm_autotune_kept_per_width():
+    """The SpMM variant tuned for one n stays in use for that n after tuning another n, and
+    an explicit variant applies to every n."""
+    A, _ = synth.gen_c1(8, n=2048)
+    p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, oracle.Thresholds(amin_band=256, amin_block=256))
+    X16 = torch.from_numpy(synth.gen_dense_matrix(1, A.ncols, 16)).cuda()
+    X130 = torch.from_numpy(synth.gen_dense_matrix(2, A.ncols, 130)).cuda()
+    Y16 = torch.empty(A.nrows, 16, device="cuda")
+    Y130 = torch.empty(A.nrows, 130, device="cuda")
+    sable.sable_autotune(p, 1, 16, X16, Y16)
+    m16 = sable.sable_plan_info(p)["spmm_variant"]
+    sable.sable_autotune(p, 1, 130, X130, Y130)
+    m130 = sable.sable_plan_info(p)["spmm_variant"]
+    print(f"  tuned modes: n=16 -> {m16}, n=130 -> {m130}")
+    sable.sable_spmm(p, X16, Y16, 16)
+    ref = torch.empty_like(Y16)
+    q = gpu_plan(A, [V, B, C], oracle.MODE_TILED, oracle.Thresholds(amin_band=256, amin_block=256))
+    sable.sable_plan_set_variant(q, 1, m16)
+    sable.sable_spmm(q, X16, ref, 16)
+    torch.cuda.synchronize()
+    assert torch.equal(Y16, ref)
+    for m in range(4):  # an explicit choice reaches every width
+        sable.sable_plan_set_variant(p, 1, m)
+        sable.sable_plan_set_variant(q, 1, m)
+        sable.sable_spmm(p, X16, Y16, 16)
+        sable.sable_spmm(q, X16, ref, 16)
+        torch.cuda.synchronize()
+        assert torch.equal(Y16, ref), m
+
+
 def test_spmm_split_bf16_block_accuracy():
     """One dense 300x200 block (all regions VBR): the split-bf16 matrix-core path keeps the
     normwise error near 2^-16 relative, far below plain bf16 (~2^-9)."""
