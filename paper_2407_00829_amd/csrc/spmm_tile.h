@@ -11,9 +11,11 @@
 //     w and w+4 and keeps their accumulators for all four row slices in registers across all
 //     blocks (block order), so there is no synchronisation between blocks and each X
 //     fragment serves every row slice; the sums are then added to the band partial.
-//     Without bf16 copies blocks run in fp32 on the VALU.
-//  3. CSR (VALU fp32, eight X rows in flight per lane) accumulated separately, then
-//     Y = (bands + blocks) + CSR is stored.
+//     Without bf16 copies, or when the fp32 VALU variant is chosen, blocks run on the VALU
+//     in the operand type (each loaded row of X multiplied into up to 8 block rows).
+//  3. CSR (VALU, several X rows in flight per lane; when one wave covers a row, its indices
+//     and values are loaded 64 at a time and broadcast with readlane) accumulated
+//     separately, then Y = (bands + blocks) + CSR is stored.
 // Every element has a fixed summation order, so results are bitwise reproducible.
 #pragma once
 
