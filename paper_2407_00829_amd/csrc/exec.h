@@ -98,6 +98,14 @@ __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const flo
   tile_rows(P, tile, r0, rend);
   const int r = r0 + threadIdx.x;
   const bool act = r < rend;
+  // W > 1: the first row of this lane group; its row pointers are loaded before anything
+  // else, so they are in flight together with the tile's format lists
+  const int grp0 = threadIdx.x / W;
+  int kb0 = 0, ke0 = 0;
+  if (W > 1 && grp0 < RT && r0 + grp0 < rend) {
+    kb0 = P.csr_ptr[r0 + grp0];
+    ke0 = P.csr_ptr[r0 + grp0 + 1];
+  }
   float acc = 0.f;
   const int slo = P.tile_seg_lo[tile], shi = P.tile_seg_hi[tile];
   for (int s = slo; s < shi; ++s) {
@@ -132,8 +140,11 @@ __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const flo
     if (act) y[r] = acc + cs;
     return;
   }
-  part[threadIdx.x] = acc;
-  __syncthreads();
+  const bool bands = slo < shi;  // same for the whole tile: without bands, no LDS exchange
+  if (bands) {
+    part[threadIdx.x] = acc;
+    __syncthreads();
+  }
   const int lane = threadIdx.x & (W - 1);
   const int grp = threadIdx.x / W;
   const int ngrp = (int)blockDim.x / W;  // row groups of W lanes
@@ -150,12 +161,14 @@ __device__ __forceinline__ void spmv_tile(const PlanView& P, int tile, const flo
         const float* v = P.vbr_val + P.blk_val_ptr[b] + (rr - br0);
         for (int c = c0 + lane; c < c1; c += W) cs += v[(i64)(c - c0) * h] * x[c];
       }
-      const int ke = P.csr_ptr[rr + 1];
-      for (int k = P.csr_ptr[rr] + lane; k < ke; k += W) cs += P.csr_val[k] * x[P.csr_col[k]];
+      const bool first = rl == grp0;
+      const int ke = first ? ke0 : P.csr_ptr[rr + 1];
+      for (int k = (first ? kb0 : P.csr_ptr[rr]) + lane; k < ke; k += W)
+        cs += P.csr_val[k] * x[P.csr_col[k]];
     }
 #pragma unroll
     for (int o = W / 2; o > 0; o >>= 1) cs += __shfl_xor(cs, o, W);
-    if (lane == 0 && rr < rend) y[rr] = part[rl] + cs;
+    if (lane == 0 && rr < rend) y[rr] = (bands ? part[rl] : 0.f) + cs;
   }
 }
 
