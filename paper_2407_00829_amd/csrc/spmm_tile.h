@@ -23,6 +23,10 @@
 
 namespace sable {
 
+// Staged block descriptor word: the same for every lane, so it goes to a scalar register
+// (block bookkeeping then runs as scalar control flow, not per lane).
+__device__ __forceinline__ int desc(const int* d, int i) { return __builtin_amdgcn_readfirstlane(d[i]); }
+
 // Lane l's value of v, for every lane (l wave-uniform).
 __device__ __forceinline__ float readlane_val(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -141,10 +145,10 @@ __device__ __forceinline__ void mfma_small_batch(const PlanView& P, const int* s
     const bool sv = s < cnt;
     const int* d = sb + kBlkDesc * ib[sv ? s : 0];
     const int k0 = ik[sv ? s : 0];
-    const int br0 = d[0], c0 = d[2], w = d[3] - d[2];
+    const int br0 = desc(d, 0), c0 = desc(d, 2), w = desc(d, 3) - c0;
     const int w4 = (w + 3) & ~3;
-    const int lo = max(br0, r0), hi = min(d[1], rend);
-    const i64 mp = (i64)(((uint64_t)(uint32_t)d[7] << 32) | (uint32_t)d[6]);
+    const int lo = max(br0, r0), hi = min(desc(d, 1), rend);
+    const i64 mp = (i64)(((uint64_t)(uint32_t)desc(d, 7) << 32) | (uint32_t)desc(d, 6));
     ma[s] = (lo - r0) >> 4;
     nsl[s] = sv ? ((hi - 1 - r0) >> 4) - ma[s] + 1 : 0;
     // every load is issued (addresses clamped into the block and into X) and masked after
@@ -203,12 +207,12 @@ __device__ __forceinline__ void spmm_blocks_valu(const PlanView& P, int* sb, int
     stage_blocks(P, q0, nq, sb);  // also orders the band phase's LDS writes before these
     for (int j = 0; j < nq; ++j) {
       const int* dsc = sb + kBlkDesc * j;
-      const int br0 = dsc[0], br1 = dsc[1];
+      const int br0 = desc(dsc, 0), br1 = desc(dsc, 1);
       const int a = max(br0, wr0), b = min(br1, wr1);
       if (a >= b) continue;
-      const int c0 = dsc[2], c1 = dsc[3];
+      const int c0 = desc(dsc, 2), c1 = desc(dsc, 3);
       const int h = br1 - br0, w = c1 - c0;
-      const i64 vp = (i64)(((uint64_t)(uint32_t)dsc[5] << 32) | (uint32_t)dsc[4]);
+      const i64 vp = (i64)(((uint64_t)(uint32_t)desc(dsc, 5) << 32) | (uint32_t)desc(dsc, 4));
       const T* vb = Vals<T>::vbr(P) + vp;  // cell (r, c0 + k) at vb[k h + r - br0]
       for (int rc = a; rc < b; rc += 8 * rpw) {
         T accA[8], accB[8];
@@ -278,7 +282,7 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
   int* sb = reinterpret_cast<int*>(ys + kMmRows * kMmCols);  // [kMmBlkStage][kBlkDesc]
   const int nc = min(kMmCols, n - cb);
   const int rend = min(r0 + kMmRows, P.nrows);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   // lanes per row (power of two >= nc/2, at most 64) and rows per wave step
   int lpr = 64;
   while (lpr > 1 && lpr / 2 >= (nc + 1) / 2) lpr >>= 1;
@@ -342,14 +346,14 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
       int cnt = 0, jj = j, kk0 = kstart;
       while (cnt < kMmBatch && jj < nq) {
         const int* d = sb + kBlkDesc * jj;
-        const int lo = max(d[0], r0), hi = min(d[1], rend);
+        const int lo = max(desc(d, 0), r0), hi = min(desc(d, 1), rend);
         if (lo >= hi) { ++jj; kk0 = 0; continue; }
         if (((hi - 1 - r0) >> 4) - ((lo - r0) >> 4) > 1) break;
         ib[cnt] = jj;
         ik[cnt] = kk0;
         ++cnt;
         kk0 += 16;
-        if (kk0 >= d[3] - d[2]) { ++jj; kk0 = 0; }
+        if (kk0 >= desc(d, 3) - desc(d, 2)) { ++jj; kk0 = 0; }
       }
       if (cnt > 0) {
         mfma_small_batch(P, sb, ib, ik, cnt, r0, rend, cb, n, nc, X, part, m, kg, acc);
@@ -362,11 +366,11 @@ __device__ __forceinline__ void spmm_tile(const PlanView& P, int r0, int cb, int
       const int* dsc = sb + kBlkDesc * jj;
       j = jj + 1;
       kstart = 0;
-      const int br0 = dsc[0], br1 = dsc[1];
+      const int br0 = desc(dsc, 0), br1 = desc(dsc, 1);
       const int lo = max(br0, r0), hi = min(br1, rend);
-      const int c0 = dsc[2], c1 = dsc[3];
+      const int c0 = desc(dsc, 2), c1 = desc(dsc, 3);
       const int w = c1 - c0, w4 = (w + 3) & ~3;
-      const i64 mp = (i64)(((uint64_t)(uint32_t)dsc[7] << 32) | (uint32_t)dsc[6]);
+      const i64 mp = (i64)(((uint64_t)(uint32_t)desc(dsc, 7) << 32) | (uint32_t)desc(dsc, 6));
       for (int k0 = 0; k0 < w; k0 += 16) {
         const int kk = k0 + 4 * kg;  // first of this lane's four k values
         // B fragments (both column chunks) and A fragments (every 16-row slice) first
