@@ -436,6 +436,7 @@ def run_spmm(args, torch, sable, synth):
     Y = torch.empty(A.nrows, n, device="cuda")
     if args.autotune:
         sable.sable_autotune(p, 1, n, Xd, Y)
+        info = sable.sable_plan_info(p)
     f_h = sable.launcher("sable_spmm", p, Xd, Y, n)
     wall, ev_ms = timed_steps(f_h, args.steps, args.warmup, torch)
     rows = np.random.default_rng(0).choice(A.nrows, 4096, replace=False)
@@ -463,12 +464,16 @@ def run_spmm(args, torch, sable, synth):
         "metric": "hybrid SpMV/SpMM GFLOP/s & %HBM peak vs plain GPU CSR; rel err vs FP64",
         "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16x3", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+bf16x3" if info["spmm_variant"] in (0, 3) and info["nblk"] else "f32",
+        "data": "synthetic",
         "config": {"workload": "FEM-like SpMM n=128: 500,000 rows, 6x6 node blocks on a periodic "
                                "27-point block stencil, 2 bands, 0.01% scatter; U(-1,1)",
                    "rows": A.nrows, "nnz": A.nnz, "n": n},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": {0: "k_spmm_tile", 1: "k_spmm_tile_valu", 2: "k_spmm_fused_valu",
+                                3: "k_spmm_tile"}[info["spmm_variant"]],
                      "launch_ms": round(ev_ms, 4)},
         "rel_err_fp64_sampled": err,
         "plain_csr": {"launch_ms": round(ev_q, 4),

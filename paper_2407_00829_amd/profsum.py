@@ -151,6 +151,8 @@ def trace_summary(argv):
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--kernel", default="")
     ap.add_argument("--flop", type=float, default=0.0)
+    ap.add_argument("--timed", default="",
+                    help="'first,count': also the mean over these dispatches of the kernel")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args(argv)
     rows = kernel_stats(a.trace)
@@ -168,6 +170,12 @@ def trace_summary(argv):
         md += ["", f"* `{a.kernel}`: average {avg:.1f} us over {sel[0]['Calls']} dispatches"
                + (f"; {a.flop / 1e9:.1f} GFLOP per dispatch -> {a.flop / (avg * 1e-6) / 1e12:.2f} TFLOP/s."
                   if a.flop else ".")]
+        if a.timed:
+            first, count = (int(v) for v in a.timed.split(","))
+            tm = timed_mean_us(a.trace, a.kernel, first, count)
+            md.append(f"* Dispatches {first}..{first + count - 1} of `{a.kernel}` (the benchmark's "
+                      f"timed launches): mean {tm:.1f} us"
+                      + (f" -> {a.flop / (tm * 1e-6) / 1e12:.2f} TFLOP/s." if a.flop else "."))
     os.makedirs(a.out, exist_ok=True)
     with open(os.path.join(a.out, f"{a.name}.md"), "w") as f:
         f.write("\n".join(md) + "\n")
