@@ -186,7 +186,9 @@ sable_status sable_spmv(sable_plan_t p, const float* x, float* y, void* stream);
 
 /* Y = A X with n >= 1 right-hand sides (row-major, App. A.2). VBR blocks run on matrix
  * cores as split-bf16 products (hi*hi + hi*lo + lo*hi, fp32 accumulate) when the plan kept
- * bf16 copies (SABLE_F_SPLIT_BF16), otherwise in fp32; VDIA and CSR run in fp32. */
+ * bf16 copies (SABLE_F_SPLIT_BF16) and the selected SpMM variant uses them (0 or 3, see
+ * sable_plan_set_variant), otherwise in fp32 on the vector units; VDIA and CSR run in fp32.
+ * X and Y must be 16-byte aligned (SABLE_ERR_INVALID_ARG otherwise). */
 sable_status sable_spmm(sable_plan_t p, const float* X, float* Y, int32_t n, void* stream);
 
 /* Plain CSR SpMV of the whole input matrix: the baseline kernel family (wave / sub-wave per
