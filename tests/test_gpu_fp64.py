@@ -181,3 +181,24 @@ def test_far_column_split_fp64(shape):
     v2 = fp64_values(A, 23)
     sable.sable_update_values_f64(p, torch.from_numpy(v2).cuda())
     check_spmv64(p, A, v2, 24)
+
+
+def test_c3_full_size_fp64_sampled():
+    """FEM-like 500,000-row matrix, FP64 SpMM with n = 128 on sampled rows (plus the first and
+    last) against the oracle's FP64-input product of those rows."""
+    A, X32 = synth.gen_c3(0)
+    th = sable.Thresholds(delta_band_pm=900, delta_block_pm=900, amin_block=36)
+    p, v = plan64(A, [V, B, C], sable.SABLE_VBR_TILED, th, 31)
+    n = X32.shape[1]
+    X = np.random.default_rng(32).standard_normal((A.ncols, n))
+    Y = torch.full((A.nrows, n), float("nan"), dtype=torch.float64, device="cuda")
+    sable.sable_spmm_f64(p, torch.from_numpy(X).cuda(), Y, n)
+    torch.cuda.synchronize()
+    rows = np.concatenate([np.random.default_rng(33).choice(A.nrows, 1024, replace=False),
+                           [0, A.nrows - 1]])
+    sub_ptr = np.concatenate([[0], np.cumsum(np.diff(A.indptr)[rows])])
+    idx = np.concatenate([np.arange(A.indptr[r], A.indptr[r + 1]) for r in rows])
+    S = synth.CSR(rows.size, A.ncols, sub_ptr.astype(A.indptr.dtype), A.indices[idx], A.values[idx])
+    err = oracle.rel_err(Y.cpu().numpy()[rows], oracle.spmm64(S, v[idx], X))
+    print(f"  sampled rel_err={err:.3e}")
+    assert err <= TOL
