@@ -266,9 +266,11 @@ def measured_traffic(name: str, kernel: str):
             rec = json.load(f)
     except OSError:
         return None
-    if rec.get("kernel") != kernel or rec.get("kernel_source_sha256") != profsum.kernel_source_sha():
-        return None
-    return rec["traffic_bytes"]
+    recs = rec if isinstance(rec, list) else [rec]  # one record per profiled kernel
+    for r in recs:
+        if r.get("kernel") == kernel and r.get("kernel_source_sha256") == profsum.kernel_source_sha():
+            return r["traffic_bytes"]
+    return None
 
 
 def run_spmv(args, torch, sable, synth):

@@ -204,6 +204,10 @@ def main(argv=None):
                     help="'first,count': also report the mean over these dispatches of the "
                          "kernel (the benchmark's timed launches)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    ap.add_argument("--append", action="store_true",
+                    help="add this kernel's traffic record to the existing file")
+    ap.add_argument("--md-name", default="",
+                    help="write the summary under this name instead of --name")
     a = ap.parse_args(argv)
     rows = kernel_stats(a.trace)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
@@ -253,13 +257,20 @@ def main(argv=None):
                       f"after the warm-up and before the cache-cold launches): mean {tm:.2f} us -> "
                       f"{(fetch_b + write_b) / (tm * 1e-6) / 1e12:.2f} TB/s of counted traffic.")
     os.makedirs(a.out, exist_ok=True)
-    with open(os.path.join(a.out, f"{a.name}.md"), "w") as f:
+    with open(os.path.join(a.out, f"{a.md_name or a.name}.md"), "w") as f:
         f.write("\n".join(md) + "\n")
     rec = {"kernel": a.kernel, "fetch_kib": f_k, "write_kib": w_k, "fetch_factor": ff,
            "write_factor": wf, "traffic_bytes": fetch_b + write_b,
            "kernel_source_sha256": kernel_source_sha(), "command": a.cmd}
-    with open(os.path.join(a.out, f"{a.name}_traffic.json"), "w") as f:
-        json.dump(rec, f, indent=1)
+    path = os.path.join(a.out, f"{a.name}_traffic.json")
+    recs = []
+    if a.append and os.path.exists(path):  # keep the records of other kernels
+        with open(path) as f:
+            old = json.load(f)
+        recs = [r for r in (old if isinstance(old, list) else [old]) if r.get("kernel") != a.kernel]
+    recs.append(rec)
+    with open(path, "w") as f:
+        json.dump(recs if len(recs) > 1 else rec, f, indent=1)
     print("\n".join(md))
 
 
