@@ -269,7 +269,9 @@ def launcher(fn: str, p: Plan, *args, stream=None):
     """A zero-argument callable for repeated calls of one product entry point (sable_spmv,
     sable_csr_spmv, sable_spmm, their _f64 forms) with its arguments marshalled once, so that
     a loop of launches of kernels that take a few microseconds is bound by the GPU rather
-    than by per-call argument conversion. args: tensors (device pointers) and ints (n)."""
+    than by per-call argument conversion. args: tensors (device pointers) and ints (n). The
+    tensors' addresses are taken once: they must stay alive (and unmoved) while the callable
+    is used; the stream is the current one at construction unless given."""
     f = getattr(lib(), fn)
     cargs = [p.h] + [ctypes.c_int32(a) if isinstance(a, int) else _ptr(a) for a in args]
     cargs.append(_stream(stream))
