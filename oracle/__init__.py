@@ -10,7 +10,9 @@ Functions (each follows the passage cited in oracle/sor.cpp):
   spmv_rows / spmm_rows          the same for selected rows (sampled checks at full size)
   spmv64(A, v, x), spmm64(A, v, X)  FP64 products with fp64 values and operands (the
                                  paper's precision, Sec. 5 / App. A), entries in CSR order
-  partition_spmv(h, x)           FP64 product over a plan's formats (fill included)
+  partition_spmv(A, kinds, vbr_mode, th, x)  FP64 product over the formats of the plan the
+                                 oracle builds for A (fill included, Sec. 3.4 shared output)
+  find_block(A, region, by_rows, th)  one pass of the block search (Alg. 2) on a region
   bf16_split(a)                  round-to-nearest-even hi/lo split of fp32 values
   rel_err(y, yref)               normwise relative error ||y - yref||_2 / ||yref||_2
 """
@@ -103,6 +105,9 @@ def _load():
     lib.sor_spmm_f64.argtypes = [i64, P, P, P, P, i64, P]
     lib.sor_spmm_rows_f64.argtypes = [i64, P, P, P, P, P, i64, P]
     lib.sor_partition_spmv_f64.argtypes = [P, P, P]
+    lib.sor_find_block.argtypes = [i64, i64, i64, P, P, i64, i64, i64, i64, ctypes.c_int32,
+                                   ctypes.POINTER(_Thr), P]
+    lib.sor_find_block.restype = ctypes.c_int
     lib.sor_bf16_split.argtypes = [i64, P, P, P]
     _lib = lib
     return lib
@@ -183,6 +188,48 @@ def plan(A, kinds, vbr_mode=MODE_AUTO, th: Thresholds | None = None) -> dict:
         return out
     finally:
         lib.sor_free(h)
+
+
+def partition_spmv(A, kinds, vbr_mode=MODE_AUTO, th: Thresholds | None = None,
+                   x: np.ndarray | None = None) -> np.ndarray:
+    """FP64 y = (VDIA part + VBR part + CSR part) x over the formats of the plan the oracle
+    builds for A (stored fill cells included, out-of-range band cells skipped). Equals
+    spmv(A, x) up to FP64 rounding order (Sec. 3.4: regions accumulate into one output)."""
+    lib = _load()
+    th = th or Thresholds()
+    ip, ix, vv = _csr_arrays(A)
+    kinds = np.asarray(kinds, dtype=np.int32)
+    modes = np.full(kinds.size, vbr_mode, dtype=np.int32)
+    h = ctypes.c_void_p()
+    cth = th._c()
+    rc = lib.sor_plan(A.nrows, A.ncols, int(ip[-1]), _p(ip), _p(ix), _p(vv), _p(kinds),
+                      _p(modes), int(kinds.size), ctypes.byref(cth), ctypes.byref(h))
+    if rc:
+        raise OracleError(rc)
+    try:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.zeros(A.nrows, np.float64)
+        lib.sor_partition_spmv_f64(h, _p(x), _p(y))
+        return y
+    finally:
+        lib.sor_free(h)
+
+
+def find_block(A, region, by_rows: bool, th: Thresholds | None = None):
+    """One FindBlock pass (Alg. 2) over region (r0, r1, c0, c1) of A: by_rows = the CSR pass
+    (outer = rows), else the CSC pass. Returns (nnz, area, o0, o1, i0, i1), region-relative,
+    with nnz = -1 when no window qualifies."""
+    lib = _load()
+    th = th or Thresholds()
+    ip, ix, _ = _csr_arrays(A)
+    out = np.zeros(6, np.int64)
+    cth = th._c()
+    r0, r1, c0, c1 = (int(t) for t in region)
+    rc = lib.sor_find_block(A.nrows, A.ncols, int(ip[-1]), _p(ip), _p(ix), r0, r1, c0, c1,
+                            1 if by_rows else 0, ctypes.byref(cth), _p(out))
+    if rc:
+        raise OracleError(rc)
+    return tuple(int(t) for t in out)
 
 
 def partition_spmv_from_export(P: dict, x: np.ndarray) -> np.ndarray:

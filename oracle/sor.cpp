@@ -297,54 +297,55 @@ i64 ceil_sqrt(i64 a) {
   return s;
 }
 
+// Best delta-dense window of one outer span (Alg. 2's inner scan, Sec. 4.1 text): H[i]
+// counts the span's entries at inner index i, s is the span's length. The right end i1 moves
+// one index at a time; for each, the left end i0 moves right (never back) while the window
+// [i0, i1] is large enough (s * width >= A_min) but below delta. The window it stops at is a
+// candidate when it is large enough (then it is dense); among candidates the first one of
+// strictly highest score is kept in `best` (o0 / o1 are filled in by the caller).
+void best_window(const std::vector<i64>& H, i64 s, const Thr& th, i64 o0, i64 o1, Cand& best) {
+  const i64 Lin = (i64)H.size();
+  i64 i0 = 0, win = 0;  // win = entries of the span in [i0, i1]
+  for (i64 i1 = 0; i1 < Lin; ++i1) {
+    win += H[i1];
+    while (i0 <= i1 && s * (i1 - i0 + 1) >= th.amin_block &&
+           !dense_enough(win, s * (i1 - i0 + 1), th.delta_block_pm)) {
+      win -= H[i0];
+      ++i0;
+    }
+    if (i0 > i1 || s * (i1 - i0 + 1) < th.amin_block) continue;
+    const i64 a = s * (i1 - i0 + 1);
+    if (score_gt(win, a, best.nnz, best.area)) {
+      best.nnz = win; best.area = a;
+      best.o0 = o0; best.o1 = o1; best.i0 = i0; best.i1 = i1;
+    }
+  }
+}
+
 // FindBlock (Alg. 2) over region [r0,r1) x [c0,c1). by_rows selects the CSR pass (outer =
 // rows, inner = columns) or the CSC pass (outer = columns, inner = rows). Indices are
-// region-relative. The outer loop is the paper's parallel for; per-start results are merged
-// in start order with a strict comparison, which equals the sequential iteration.
+// region-relative. For every outer start o0 (the paper's parallel loop) the span grows one
+// outer slice at a time, H accumulating the slice's inner indices; spans of at least
+// s_min slices are scanned by best_window. Per-start results are merged in start order with
+// a strict comparison, which equals the sequential iteration.
 Cand find_block(const Mat& R, const Csc& C, const Blk& reg, bool by_rows, const Thr& th) {
   const i64 Lout = by_rows ? reg.r1 - reg.r0 : reg.c1 - reg.c0;
   const i64 Lin = by_rows ? reg.c1 - reg.c0 : reg.r1 - reg.r0;
-  const i64 amin = th.amin_block;
-  const int p = th.delta_block_pm;
-  const i64 smin = ceil_sqrt(amin);
+  const i64 smin = ceil_sqrt(th.amin_block);
   std::vector<Cand> per(Lout > 0 ? Lout : 0);
 #pragma omp parallel for schedule(dynamic, 1)
   for (i64 o0 = 0; o0 < Lout; ++o0) {
     std::vector<i64> H(Lin, 0);
     Cand best;
     for (i64 o1 = o0; o1 < Lout; ++o1) {
-      if (by_rows) {
-        i64 r = reg.r0 + o1;
-        const int32_t* b = R.col.data() + R.ptr[r];
-        const int32_t* e = R.col.data() + R.ptr[r + 1];
-        for (const int32_t* q = std::lower_bound(b, e, (int32_t)reg.c0); q < e && *q < reg.c1; ++q)
-          H[*q - reg.c0] += 1;
-      } else {
-        i64 c = reg.c0 + o1;
-        const int32_t* b = C.row.data() + C.ptr[c];
-        const int32_t* e = C.row.data() + C.ptr[c + 1];
-        for (const int32_t* q = std::lower_bound(b, e, (int32_t)reg.r0); q < e && *q < reg.r1; ++q)
-          H[*q - reg.r0] += 1;
-      }
-      const i64 s = o1 - o0 + 1;
-      if (s < smin) continue;
-      i64 nnz = 0, i0 = 0;
-      for (i64 i1 = 0; i1 < Lin; ++i1) {
-        nnz += H[i1];
-        while (i0 <= i1) {
-          const i64 a = s * (i1 - i0 + 1);
-          if (a < amin) break;
-          if (dense_enough(nnz, a, p)) {
-            if (score_gt(nnz, a, best.nnz, best.area)) {
-              best.nnz = nnz; best.area = a;
-              best.o0 = o0; best.o1 = o1; best.i0 = i0; best.i1 = i1;
-            }
-            break;
-          }
-          nnz -= H[i0];
-          i0 += 1;
-        }
-      }
+      // slice o1 of the region: the entries of one row (CSR) or one column (CSC)
+      const bool row = by_rows;
+      const i64 at = (row ? reg.r0 : reg.c0) + o1;
+      const i64 lo = row ? reg.c0 : reg.r0, hi = row ? reg.c1 : reg.r1;
+      const int32_t* b = row ? R.col.data() + R.ptr[at] : C.row.data() + C.ptr[at];
+      const int32_t* e = row ? R.col.data() + R.ptr[at + 1] : C.row.data() + C.ptr[at + 1];
+      for (const int32_t* q = std::lower_bound(b, e, (int32_t)lo); q < e && *q < hi; ++q) H[*q - lo] += 1;
+      if (o1 - o0 + 1 >= smin) best_window(H, o1 - o0 + 1, th, o0, o1, best);
     }
     per[o0] = best;
   }
@@ -646,6 +647,27 @@ int sor_plan(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* indptr,
   int rc = build_plan(nrows, ncols, nnz, indptr, indices, values, kinds, modes, nlist, *th, *P);
   if (rc) { delete P; return rc; }
   *out = P;
+  return 0;
+}
+
+// FindBlock (Alg. 2) of one pass over region [r0,r1) x [c0,c1) of a canonical CSR matrix
+// (tests pin it against an independent formulation). out = (nnz, area, o0, o1, i0, i1),
+// region-relative; nnz = -1 when no window qualifies. Returns 0, or 1 for a bad region.
+int sor_find_block(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* indptr,
+                   const int32_t* indices, int64_t r0, int64_t r1, int64_t c0, int64_t c1,
+                   int32_t by_rows, const Thr* th, int64_t* out) {
+  if (r0 < 0 || c0 < 0 || r1 > nrows || c1 > ncols || r0 > r1 || c0 > c1 || !th || !out) return 1;
+  Mat R;
+  R.nrows = nrows;
+  R.ncols = ncols;
+  R.ptr.assign(indptr, indptr + nrows + 1);
+  R.col.assign(indices, indices + nnz);
+  R.val.assign(nnz, 1.0f);
+  R.id.resize(nnz);
+  for (int64_t k = 0; k < nnz; ++k) R.id[k] = k;
+  Csc C = transpose(R);
+  Cand c = find_block(R, C, {r0, r1, c0, c1}, by_rows != 0, *th);
+  out[0] = c.nnz; out[1] = c.area; out[2] = c.o0; out[3] = c.o1; out[4] = c.i0; out[5] = c.i1;
   return 0;
 }
 
