@@ -215,6 +215,19 @@ sable_status sable_spmm_f64(sable_plan_t p, const double* X, double* Y, int32_t 
 sable_status sable_error_norm_f64(const float* y, const double* yref, int64_t len,
                                   void* stream, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops or harnesses that forbid hipMalloc): the same relative error as sable_error_norm_f64,
+ * from the same kernels, written to a DEVICE double *out_dev; asynchronous on `stream` (no
+ * synchronisation, no host copy, no allocation of any kind). The partial sums live in a
+ * library-owned static device array of 1024 pairs of doubles (16 KiB, one copy per GPU,
+ * held until the process ends); the reduction grid is capped at 1024 workgroups, so every
+ * len >= 0 fits. Each call overwrites that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from several threads) race and must be serialised by the caller.
+ * Errors: SABLE_ERR_INVALID_ARG (out_dev NULL, len < 0, NULL y / yref with len > 0),
+ * SABLE_ERR_HIP. */
+sable_status sable_error_norm_f64_noalloc(const float* y, const double* yref, int64_t len,
+                                          void* stream, double* out_dev);
+
 /* Replace the values of A (same structure as at planning time, device values[nnz]) in every
  * format without re-extracting: the inspector-executor reuse of Sec. 5 "Evaluation
  * scenario". Asynchronous on `stream`. */

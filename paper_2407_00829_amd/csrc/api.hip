@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "plan.h"
 
@@ -83,12 +84,47 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_partial(const float* __re
   }
 }
 
+// Adds the nb partial pairs in block order and writes the relative error
+// sqrt(sum d^2) / sqrt(sum yref^2) (the absolute one if yref = 0) to out[0].
 __global__ void k_norm_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
   if (threadIdx.x || blockIdx.x) return;
   double a = 0.0, b = 0.0;
   for (int k = 0; k < nb; ++k) { a += part[2 * k]; b += part[2 * k + 1]; }
-  out[0] = a;
-  out[1] = b;
+  const double num = sqrt(a), den = sqrt(b);
+  out[0] = den > 0.0 ? num / den : num;
+}
+
+// Partial-sum pairs of the error norm: one per workgroup of k_norm_partial, whose grid is
+// capped at this count, so every input length fits.
+constexpr int kNormMaxParts = 1024;
+
+int norm_parts(i64 len) {
+  return (int)std::min<i64>(kNormMaxParts, std::max<i64>(1, (len + kNormThreads - 1) / kNormThreads));
+}
+
+// Scratch of the allocation-free error norm: the partial pairs, then the result slot (unused
+// there: that entry point writes the result to the caller's device double). Every GPU the
+// library runs on holds its own copy until the process ends.
+static __device__ __align__(256) double scratch[2 * kNormMaxParts + 2];
+
+// Device address of this GPU's scratch copy, looked up once per device with that device
+// current (the array's name in host code is only a host-side stand-in).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+double* scratch_for_current_device() {
+  int dev = -1;
+  HIPC(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) SB_THROW(SABLE_ERR_INTERNAL, "device id %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPC(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) SB_THROW(SABLE_ERR_HIP, "no device address for the error-norm scratch");
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  return g_scratch_ptr[dev];
 }
 
 void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list, int nlist,
@@ -415,17 +451,32 @@ sable_status sable_error_norm_f64(const float* y, const double* yref, int64_t le
   return guard([&] {
     if (!out || len < 0 || (len > 0 && (!y || !yref))) SB_THROW(SABLE_ERR_INVALID_ARG, "bad argument");
     hipStream_t s = (hipStream_t)stream;
-    const int nb = (int)std::min<i64>(1024, std::max<i64>(1, (len + kNormThreads - 1) / kNormThreads));
-    DBuf<double> part(2 * (size_t)nb), res(2);
+    const int nb = norm_parts(len);
+    DBuf<double> part(2 * (size_t)nb), res(1);
     k_norm_partial<<<nb, kNormThreads, 0, s>>>(y, yref, len, part.p);
     LAUNCH_CHECK();
     k_norm_final<<<1, 1, 0, s>>>(part.p, nb, res.p);
     LAUNCH_CHECK();
-    double h[2];
-    HIPC(hipMemcpyAsync(h, res.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    double h = 0.0;
+    HIPC(hipMemcpyAsync(&h, res.p, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    const double num = std::sqrt(h[0]), den = std::sqrt(h[1]);
-    *out = den > 0 ? num / den : num;
+    *out = h;
+  });
+}
+
+sable_status sable_error_norm_f64_noalloc(const float* y, const double* yref, int64_t len,
+                                          void* stream, double* out_dev) {
+  return guard([&] {
+    if (!out_dev || len < 0 || (len > 0 && (!y || !yref)))
+      SB_THROW(SABLE_ERR_INVALID_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = norm_parts(len);
+    double* part = scratch_for_current_device();
+    // k_norm_partial writes all 2 nb slots it uses, so nothing needs clearing
+    k_norm_partial<<<nb, kNormThreads, 0, s>>>(y, yref, len, part);
+    LAUNCH_CHECK();
+    k_norm_final<<<1, 1, 0, s>>>(part, nb, out_dev);
+    LAUNCH_CHECK();
   });
 }
 

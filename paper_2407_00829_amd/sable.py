@@ -32,6 +32,7 @@ EXPORTED = [
     "sable_mlp_forward", "sable_mlp_train_step", "sable_plan_exhaustive", "sable_plan_auto", "sable_batch_create", "sable_batch_run",
     "sable_batch_latencies", "sable_batch_destroy", "sable_last_error",
     "sable_update_values_f64", "sable_spmv_f64", "sable_spmm_f64", "sable_plan_specialize",
+    "sable_error_norm_f64_noalloc",
 ]
 
 
@@ -107,6 +108,7 @@ def lib():
         "sable_spmm": [P, P, P, i32, P],
         "sable_csr_spmv": [P, P, P, P],
         "sable_error_norm_f64": [P, P, i64, P, P],
+        "sable_error_norm_f64_noalloc": [P, P, i64, P, P],
         "sable_update_values": [P, P, P],
         "sable_autotune": [P, i32, i32, P, P, P],
         "sable_plan_set_variant": [P, i32, i32],
@@ -308,6 +310,12 @@ def sable_error_norm_f64(y, yref, stream=None) -> float:
     _check("sable_error_norm_f64", lib().sable_error_norm_f64(
         _ptr(y), _ptr(yref), int(y.numel()), _stream(stream), ctypes.byref(out)))
     return out.value
+
+
+def sable_error_norm_f64_noalloc(y, yref, out, stream=None) -> None:
+    """out: a device float64 tensor of at least one element that receives the error."""
+    _check("sable_error_norm_f64_noalloc", lib().sable_error_norm_f64_noalloc(
+        _ptr(y), _ptr(yref), int(y.numel()), _stream(stream), _ptr(out)))
 
 
 def sable_autotune(p: Plan, op: int, n: int, x, y, stream=None) -> None:
