@@ -12,7 +12,10 @@ Functions (each follows the passage cited in oracle/sor.cpp):
                                  paper's precision, Sec. 5 / App. A), entries in CSR order
   partition_spmv(A, kinds, vbr_mode, th, x)  FP64 product over the formats of the plan the
                                  oracle builds for A (fill included, Sec. 3.4 shared output)
-  find_block(A, region, by_rows, th)  one pass of the block search (Alg. 2) on a region
+  find_block(A, region, by_rows, th, sparse)  one pass of the block search (Alg. 2) on a
+                                 region; sparse = the window rule over non-empty inner
+                                 indices only (same result, pinned against the dense scan)
+  best_window(H, s, th, sparse)  the window scan of Alg. 2 for one span's inner counts
   bf16_split(a)                  round-to-nearest-even hi/lo split of fp32 values
   rel_err(y, yref)               normwise relative error ||y - yref||_2 / ||yref||_2
 """
@@ -108,6 +111,9 @@ def _load():
     lib.sor_find_block.argtypes = [i64, i64, i64, P, P, i64, i64, i64, i64, ctypes.c_int32,
                                    ctypes.POINTER(_Thr), P]
     lib.sor_find_block.restype = ctypes.c_int
+    lib.sor_find_block_sparse.argtypes = lib.sor_find_block.argtypes
+    lib.sor_find_block_sparse.restype = ctypes.c_int
+    lib.sor_best_window.argtypes = [i64, P, i64, ctypes.POINTER(_Thr), ctypes.c_int32, P]
     lib.sor_bf16_split.argtypes = [i64, P, P, P]
     _lib = lib
     return lib
@@ -215,20 +221,34 @@ def partition_spmv(A, kinds, vbr_mode=MODE_AUTO, th: Thresholds | None = None,
         lib.sor_free(h)
 
 
-def find_block(A, region, by_rows: bool, th: Thresholds | None = None):
+def find_block(A, region, by_rows: bool, th: Thresholds | None = None, sparse: bool = False):
     """One FindBlock pass (Alg. 2) over region (r0, r1, c0, c1) of A: by_rows = the CSR pass
     (outer = rows), else the CSC pass. Returns (nnz, area, o0, o1, i0, i1), region-relative,
-    with nnz = -1 when no window qualifies."""
+    with nnz = -1 when no window qualifies. sparse: evaluate the window rule over the
+    non-empty inner indices only (the same result; pinned against the dense scan)."""
     lib = _load()
     th = th or Thresholds()
     ip, ix, _ = _csr_arrays(A)
     out = np.zeros(6, np.int64)
     cth = th._c()
     r0, r1, c0, c1 = (int(t) for t in region)
-    rc = lib.sor_find_block(A.nrows, A.ncols, int(ip[-1]), _p(ip), _p(ix), r0, r1, c0, c1,
-                            1 if by_rows else 0, ctypes.byref(cth), _p(out))
+    fn = lib.sor_find_block_sparse if sparse else lib.sor_find_block
+    rc = fn(A.nrows, A.ncols, int(ip[-1]), _p(ip), _p(ix), r0, r1, c0, c1,
+            1 if by_rows else 0, ctypes.byref(cth), _p(out))
     if rc:
         raise OracleError(rc)
+    return tuple(int(t) for t in out)
+
+
+def best_window(H, s: int, th: Thresholds | None = None, sparse: bool = False):
+    """The window scan of Alg. 2 for one span of s slices with inner counts H: (nnz, area,
+    i0, i1), nnz = -1 when no window qualifies."""
+    lib = _load()
+    th = th or Thresholds()
+    H = np.ascontiguousarray(H, dtype=np.int64)
+    out = np.zeros(4, np.int64)
+    cth = th._c()
+    lib.sor_best_window(H.size, _p(H), int(s), ctypes.byref(cth), 1 if sparse else 0, _p(out))
     return tuple(int(t) for t in out)
 
 

@@ -30,6 +30,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <new>
 #include <utility>
@@ -355,6 +356,117 @@ Cand find_block(const Mat& R, const Csc& C, const Blk& reg, bool by_rows, const 
   return best;
 }
 
+// The same window rule evaluated over the span's nonzero inner positions only (q ascending,
+// hc[k] > 0 entries at q[k]); runs of empty inner indices are crossed in O(1) each.
+//
+// Why this is exact. For a window of width w holding `win` entries the scan keeps shrinking
+// from the left iff w > T(win) = max(ceil(A_min / s) - 1, floor(1000 win / (p s))): "large
+// enough but below delta" is a threshold on w once win is fixed. So while the right end
+// crosses empty columns the window grows one column per step up to T(win), and once there
+// every further step drops exactly one empty left column (or, at a non-empty one, runs the
+// general loop). Between two changes of win the widths seen at the candidate test never
+// decrease, and for fixed n a larger area scores lower ((2n - a)^3 / a decreases in a), so
+// within such a stretch only its first candidate can be a strict improvement; the first
+// strict maximum of the dense scan is therefore among the candidates tested here, at the same
+// (i0, i1), and the tie rule (first strict maximum) is unchanged.
+void best_window_sparse(const std::vector<i64>& q, const std::vector<i64>& hc, i64 Lin, i64 s,
+                        const Thr& th, i64 o0, i64 o1, Cand& best) {
+  const i64 m = (i64)q.size();
+  const i64 p = th.delta_block_pm;
+  const i64 A = th.amin_block > 0 ? (th.amin_block + s - 1) / s : 0;  // smallest large width
+  const i64 wmin = std::max<i64>(A, 1);                                // smallest candidate
+  auto T = [&](i64 win) -> i64 {
+    const i64 D = p > 0 ? (1000 * win) / (p * s) : std::numeric_limits<i64>::max() / 4;
+    return std::max(A - 1, D);
+  };
+  i64 i0 = 0, i1 = -1, win = 0;
+  i64 kl = 0, kr = 0;  // first nonzero at or after i0; next nonzero to enter on the right
+  bool tested = false;  // the current stretch of constant win has had its first candidate
+  auto left_gap = [&]() { return (kl < m ? q[kl] : Lin) - i0; };  // empty columns from i0
+  auto shrink = [&]() {
+    for (;;) {
+      const i64 w = i1 - i0 + 1, t = T(win);
+      if (w <= t) return;
+      const i64 z = left_gap();
+      if (z > 0) { i0 += std::min(z, w - t); continue; }
+      win -= hc[kl]; ++kl; ++i0; tested = false;
+    }
+  };
+  auto test = [&]() {
+    const i64 w = i1 - i0 + 1;
+    if (tested || w < wmin) return;
+    tested = true;
+    const i64 a = s * w;
+    if (score_gt(win, a, best.nnz, best.area)) {
+      best.nnz = win; best.area = a;
+      best.o0 = o0; best.o1 = o1; best.i0 = i0; best.i1 = i1;
+    }
+  };
+  for (;;) {
+    i64 rem = (kr < m ? q[kr] : Lin) - (i1 + 1);  // empty columns before the next nonzero
+    while (rem > 0) {
+      const i64 w = i1 - i0 + 1, t = T(win);
+      if (w < t) {  // grow without any removal
+        const i64 k = std::min(rem, t - w);
+        const i64 wc = std::max(w + 1, wmin);
+        if (!tested && wc <= w + k) { i1 += wc - w; test(); i1 += w + k - wc; }
+        else i1 += k;
+        rem -= k;
+        continue;
+      }
+      const i64 z = left_gap();  // w == t: every step now removes at the left
+      if (z > 0) {  // each of the next min(rem, z) steps drops one empty column
+        const i64 k = std::min(rem, z);
+        ++i1; ++i0; test();
+        i1 += k - 1; i0 += k - 1;
+        rem -= k;
+        continue;
+      }
+      ++i1; shrink(); test(); --rem;
+    }
+    if (kr >= m) break;
+    i1 = q[kr]; win += hc[kr]; ++kr; tested = false;
+    shrink(); test();
+  }
+}
+
+// FindBlock (Alg. 2) with the sparse window scan: the same result as find_block, in time
+// proportional to the distinct non-empty inner indices of each span.
+Cand find_block_sparse(const Mat& R, const Csc& C, const Blk& reg, bool by_rows, const Thr& th) {
+  const i64 Lout = by_rows ? reg.r1 - reg.r0 : reg.c1 - reg.c0;
+  const i64 Lin = by_rows ? reg.c1 - reg.c0 : reg.r1 - reg.r0;
+  const i64 smin = ceil_sqrt(th.amin_block);
+  std::vector<Cand> per(Lout > 0 ? Lout : 0);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (i64 o0 = 0; o0 < Lout; ++o0) {
+    std::vector<i64> H(Lin, 0), pos, fresh, merged, hc;
+    Cand best;
+    for (i64 o1 = o0; o1 < Lout; ++o1) {
+      const i64 at = (by_rows ? reg.r0 : reg.c0) + o1;
+      const i64 lo = by_rows ? reg.c0 : reg.r0, hi = by_rows ? reg.c1 : reg.r1;
+      const int32_t* b = by_rows ? R.col.data() + R.ptr[at] : C.row.data() + C.ptr[at];
+      const int32_t* e = by_rows ? R.col.data() + R.ptr[at + 1] : C.row.data() + C.ptr[at + 1];
+      fresh.clear();
+      for (const int32_t* t = std::lower_bound(b, e, (int32_t)lo); t < e && *t < hi; ++t) {
+        if (H[*t - lo] == 0) fresh.push_back(*t - lo);
+        H[*t - lo] += 1;
+      }
+      merged.resize(pos.size() + fresh.size());
+      std::merge(pos.begin(), pos.end(), fresh.begin(), fresh.end(), merged.begin());
+      pos.swap(merged);
+      if (o1 - o0 + 1 < smin) continue;
+      hc.resize(pos.size());
+      for (size_t k = 0; k < pos.size(); ++k) hc[k] = H[pos[k]];
+      best_window_sparse(pos, hc, Lin, o1 - o0 + 1, th, o0, o1, best);
+    }
+    per[o0] = best;
+  }
+  Cand best;
+  for (i64 o0 = 0; o0 < Lout; ++o0)
+    if (score_gt(per[o0].nnz, per[o0].area, best.nnz, best.area)) best = per[o0];
+  return best;
+}
+
 Blk cand_rect(const Cand& c, const Blk& reg, bool by_rows) {
   if (by_rows) return {reg.r0 + c.o0, reg.r0 + c.o1 + 1, reg.c0 + c.i0, reg.c0 + c.i1 + 1};
   return {reg.r0 + c.i0, reg.r0 + c.i1 + 1, reg.c0 + c.o0, reg.c0 + c.o1 + 1};
@@ -653,9 +765,9 @@ int sor_plan(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* indptr,
 // FindBlock (Alg. 2) of one pass over region [r0,r1) x [c0,c1) of a canonical CSR matrix
 // (tests pin it against an independent formulation). out = (nnz, area, o0, o1, i0, i1),
 // region-relative; nnz = -1 when no window qualifies. Returns 0, or 1 for a bad region.
-int sor_find_block(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* indptr,
-                   const int32_t* indices, int64_t r0, int64_t r1, int64_t c0, int64_t c1,
-                   int32_t by_rows, const Thr* th, int64_t* out) {
+static int find_block_c(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* indptr,
+                        const int32_t* indices, int64_t r0, int64_t r1, int64_t c0, int64_t c1,
+                        int32_t by_rows, const Thr* th, int64_t* out, bool sparse) {
   if (r0 < 0 || c0 < 0 || r1 > nrows || c1 > ncols || r0 > r1 || c0 > c1 || !th || !out) return 1;
   Mat R;
   R.nrows = nrows;
@@ -666,9 +778,40 @@ int sor_find_block(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* ind
   R.id.resize(nnz);
   for (int64_t k = 0; k < nnz; ++k) R.id[k] = k;
   Csc C = transpose(R);
-  Cand c = find_block(R, C, {r0, r1, c0, c1}, by_rows != 0, *th);
+  const Blk reg{r0, r1, c0, c1};
+  Cand c = sparse ? find_block_sparse(R, C, reg, by_rows != 0, *th)
+                  : find_block(R, C, reg, by_rows != 0, *th);
   out[0] = c.nnz; out[1] = c.area; out[2] = c.o0; out[3] = c.o1; out[4] = c.i0; out[5] = c.i1;
   return 0;
+}
+
+int sor_find_block(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* indptr,
+                   const int32_t* indices, int64_t r0, int64_t r1, int64_t c0, int64_t c1,
+                   int32_t by_rows, const Thr* th, int64_t* out) {
+  return find_block_c(nrows, ncols, nnz, indptr, indices, r0, r1, c0, c1, by_rows, th, out, false);
+}
+
+// One window scan of Alg. 2 over given span counts H[Lin] for a span of s slices (the inner
+// loop of FindBlock, exposed for direct pins): out = (nnz, area, i0, i1), nnz = -1 if none.
+void sor_best_window(int64_t Lin, const int64_t* H, int64_t s, const Thr* th, int32_t sparse,
+                     int64_t* out) {
+  Cand best;
+  if (sparse) {
+    std::vector<i64> q, hc;
+    for (i64 i = 0; i < Lin; ++i)
+      if (H[i]) { q.push_back(i); hc.push_back(H[i]); }
+    best_window_sparse(q, hc, Lin, s, *th, 0, 0, best);
+  } else {
+    best_window(std::vector<i64>(H, H + Lin), s, *th, 0, 0, best);
+  }
+  out[0] = best.nnz; out[1] = best.area; out[2] = best.i0; out[3] = best.i1;
+}
+
+// The same pass through the sparse window scan (find_block_sparse).
+int sor_find_block_sparse(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* indptr,
+                          const int32_t* indices, int64_t r0, int64_t r1, int64_t c0, int64_t c1,
+                          int32_t by_rows, const Thr* th, int64_t* out) {
+  return find_block_c(nrows, ncols, nnz, indptr, indices, r0, r1, c0, c1, by_rows, th, out, true);
 }
 
 // counts: [nseg, vdia_nval, nidiag, nblk, vbr_nval, csr_nnz, vbr_tile, vbr_mode_used]

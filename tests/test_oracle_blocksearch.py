@@ -193,3 +193,145 @@ def test_partition_product_equals_coo_product(kinds, mode):
     assert oracle.rel_err(oracle.partition_spmv_from_export(P, x), y) <= 1e-14
     if 2 in kinds and P["blk"].shape[0]:
         assert P["vbr_val"].size > 0  # the plan really has blocks, so fill is exercised
+
+
+# ---- the sparse window scan (empty inner indices crossed in O(1) per run) -------------------
+
+def _wide_sparse_case(seed):
+    """Wide or tall sparse matrices with long runs of empty columns and rows, a few dense
+    clusters (some narrower than A_min allows, so windows must take in empty columns), and
+    thresholds from delta = 0.5 to 1."""
+    rng = np.random.default_rng(seed)
+    nr, nc = int(rng.integers(8, 70)), int(rng.integers(8, 400))
+    if rng.random() < 0.5:
+        nr, nc = nc, nr
+    rows, cols = [], []
+    nsc = int(rng.integers(0, max(1, nr * nc // 40)))
+    rows.append(rng.integers(0, nr, nsc))
+    cols.append(rng.integers(0, nc, nsc))
+    for _ in range(int(rng.integers(0, 4))):
+        h, w = int(rng.integers(1, 9)), int(rng.integers(1, 9))
+        r, c = int(rng.integers(0, nr - h + 1)), int(rng.integers(0, nc - w + 1))
+        rr, cc = np.meshgrid(np.arange(r, r + h), np.arange(c, c + w), indexing="ij")
+        keep = rng.random(rr.size) < float(rng.choice([0.6, 0.9, 1.0]))
+        rows.append(rr.ravel()[keep])
+        cols.append(cc.ravel()[keep])
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    A = synth.from_coo(nr, nc, r, c, np.ones(r.size, np.float32))
+    reg = (int(rng.integers(0, nr // 4 + 1)), nr, int(rng.integers(0, nc // 4 + 1)), nc)
+    th = oracle.Thresholds(delta_block_pm=int(rng.choice([500, 501, 667, 750, 900, 1000])),
+                           amin_block=int(rng.choice([1, 2, 4, 9, 16, 30, 64])))
+    return A, reg, th
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_sparse_scan_equals_dense_scan(seed):
+    A, reg, th = _wide_sparse_case(seed)
+    for by_rows in (True, False):
+        dense = oracle.find_block(A, reg, by_rows, th)
+        assert oracle.find_block(A, reg, by_rows, th, sparse=True) == dense, (reg, by_rows)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_sparse_scan_equals_window_rule(seed):
+    A, reg, th = _random_case(seed)
+    D = _dense(A)
+    for by_rows in (True, False):
+        got = oracle.find_block(A, reg, by_rows, th, sparse=True)
+        want = window_rule(D, reg, by_rows, th)
+        if want is None:
+            assert got[0] == -1, got
+        else:
+            assert got == want, (got, want)
+
+
+@pytest.mark.parametrize("h,w,r,c", [(5, 7, 3, 2), (9, 4, 0, 10), (6, 6, 8, 8), (4, 12, 1, 1)])
+def test_sparse_scan_planted_block(h, w, r, c):
+    """The closed-form case: a fully dense block in an empty matrix, found by the sparse
+    scan exactly as by the dense one, and returned by the full Partition."""
+    rr, cc = np.meshgrid(np.arange(r, r + h), np.arange(c, c + w), indexing="ij")
+    A = synth.from_coo(20, 20, rr.ravel(), cc.ravel(), np.ones(h * w))
+    th = oracle.Thresholds(delta_block_pm=500, amin_block=9)
+    for by_rows in (True, False):
+        got = oracle.find_block(A, (0, 20, 0, 20), by_rows, th, sparse=True)
+        assert got == oracle.find_block(A, (0, 20, 0, 20), by_rows, th)
+        assert got[0] == h * w
+
+
+@pytest.mark.parametrize("by_rows", [True, False])
+def test_sparse_scan_cluster_at_the_inner_edge(by_rows):
+    """A 3 x 3 dense cluster touching the first inner index of the region, A_min = 16 and
+    delta = 0.5: with a span of 4 slices the window first becomes large enough (4 x 4) at
+    the empty inner index just past the cluster, where it is also dense (9 / 16), and no
+    later window of that span qualifies. The sparse scan must test that candidate in the
+    middle of an empty run."""
+    r, c = (10, 0) if by_rows else (0, 10)
+    rr, cc = np.meshgrid(np.arange(r, r + 3), np.arange(c, c + 3), indexing="ij")
+    A = synth.from_coo(30, 30, rr.ravel(), cc.ravel(), np.ones(9))
+    th = oracle.Thresholds(delta_block_pm=500, amin_block=16)
+    dense = oracle.find_block(A, (0, 30, 0, 30), by_rows, th)
+    n, a, o0, o1, i0, i1 = dense
+    assert (n, a, i0, i1) == (9, 16, 0, 3)  # the window ends on the empty index 3
+    assert oracle.find_block(A, (0, 30, 0, 30), by_rows, th, sparse=True) == dense
+
+
+@pytest.mark.parametrize("chunk", range(8))
+def test_sparse_scan_equals_dense_scan_many(chunk):
+    """Many small random cases per chunk (both passes): every branch of the sparse scan,
+    including the first candidate after a non-empty column leaves the window at the left
+    while the right end crosses empty columns."""
+    for seed in range(10_000 + 150 * chunk, 10_000 + 150 * (chunk + 1)):
+        A, reg, th = _wide_sparse_case(seed)
+        for by_rows in (True, False):
+            dense = oracle.find_block(A, reg, by_rows, th)
+            assert oracle.find_block(A, reg, by_rows, th, sparse=True) == dense, (seed, by_rows)
+
+
+def _window_rule_counts(H, s, th):
+    """Sec. 4.1's window rule over one span's inner counts (Python integers)."""
+    p, amin = th.delta_block_pm, th.amin_block
+    pre = np.concatenate([[0], np.cumsum(H)]).astype(object)
+    best, left = None, 0
+    for i1 in range(len(H)):
+        j = left
+        while j <= i1:
+            a = s * (i1 - j + 1)
+            if a < amin or 1000 * (pre[i1 + 1] - pre[j]) >= p * a:
+                break
+            j += 1
+        left = j
+        if j > i1 or s * (i1 - j + 1) < amin:
+            continue
+        n, a = int(pre[i1 + 1] - pre[j]), s * (i1 - j + 1)
+        if best is None or _score(n, a) > _score(best[0], best[1]):
+            best = (n, a, j, i1)
+    return best
+
+
+def test_window_scan_hand_case_after_left_removal():
+    """Counts 0 1 0 2 2 2 2 2 0 over a span of 2 slices, A_min = 12, delta = 0.75: the best
+    window [3, 8] (10 entries, area 12) is found at the last, empty, index, right after the
+    non-empty index 1 left the window; the first candidate after a left removal must be
+    tested."""
+    th = oracle.Thresholds(delta_block_pm=750, amin_block=12)
+    H = [0, 1, 0, 2, 2, 2, 2, 2, 0]
+    assert _window_rule_counts(H, 2, th) == (10, 12, 3, 8)
+    assert oracle.best_window(H, 2, th) == (10, 12, 3, 8)
+    assert oracle.best_window(H, 2, th, sparse=True) == (10, 12, 3, 8)
+
+
+@pytest.mark.parametrize("chunk", range(6))
+def test_window_scan_sparse_equals_rule_random(chunk):
+    """Random span counts (mostly empty), every threshold pair: the dense and the sparse scans
+    both equal the declarative rule."""
+    rng = np.random.default_rng(500 + chunk)
+    for _ in range(2000):
+        L, s = int(rng.integers(1, 15)), int(rng.integers(1, 7))
+        H = np.where(rng.random(L) < 0.6, rng.integers(0, s + 1, L), 0)
+        th = oracle.Thresholds(delta_block_pm=int(rng.choice([500, 501, 550, 600, 667, 750, 900, 1000])),
+                               amin_block=int(rng.choice([1, 2, 3, 4, 6, 8, 9, 12, 16, 20])))
+        want = _window_rule_counts(H.tolist(), s, th)
+        want = want if want is not None else (-1,)
+        for sparse in (False, True):
+            got = oracle.best_window(H, s, th, sparse=sparse)
+            assert got[:len(want)] == want, (H.tolist(), s, th, sparse, got, want)
