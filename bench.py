@@ -203,36 +203,74 @@ def rocsparse_csrmm_ms(A, ip, ix, vv, Xd, n, steps, warmup, torch):
     return ms, (C.t() if ms else None)
 
 
-def cpu_baseline_spmv(A, x, target_s=10.0):
-    import oracle
-    threads = oracle.max_threads()
-    oracle.spmv(A, x)
+def host_cpu_record():
+    """What the host CPU is: model, logical CPUs, threads per core, sockets (from lscpu),
+    and the CPUs this process may run on."""
+    import subprocess
+    rec = {"nproc": len(os.sched_getaffinity(0))}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return rec
+    keep = {"Model name": "model", "CPU(s)": "cpus", "Thread(s) per core": "threads_per_core",
+            "Core(s) per socket": "cores_per_socket", "Socket(s)": "sockets",
+            "CPU max MHz": "max_mhz", "L3": "l3"}
+    for line in out.splitlines():
+        k, _, v = line.partition(":")
+        if k.strip() in keep:
+            rec[keep[k.strip()]] = v.strip()
+    return rec
+
+
+def _oracle_rate(run, flop_per_pass, target_s):
+    run()
     t0 = time.perf_counter()
     passes = 0
     while time.perf_counter() - t0 < target_s:
-        oracle.spmv(A, x)
+        run()
         passes += 1
     dt = time.perf_counter() - t0
-    return {"value": round(2.0 * A.nnz * passes / dt / 1e9, 3), "unit": "GFLOP/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"FP64 COO SpMV over the full matrix, {passes} passes ({dt:.1f} s)"}
+    return flop_per_pass * passes / dt / 1e9, passes, dt
+
+
+def cpu_baseline_spmv(A, x, target_s=10.0):
+    """The oracle's FP64 SpMV timed on the host: on every available thread (the reported
+    value) and on one thread, with the host's lscpu record."""
+    import oracle
+    threads = oracle.max_threads()
+    run = lambda: oracle.spmv(A, x)  # noqa: E731
+    g, passes, dt = _oracle_rate(run, 2.0 * A.nnz, 0.6 * target_s)
+    oracle.set_threads(1)
+    try:
+        g1, passes1, dt1 = _oracle_rate(run, 2.0 * A.nnz, 0.4 * target_s)
+    finally:
+        oracle.set_threads(threads)
+    return {"value": round(g, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 COO SpMV over the full matrix, {passes} passes ({dt:.1f} s)",
+            "single_thread": {"value": round(g1, 3), "unit": "GFLOP/s", "cores": 1,
+                              "sample": f"{passes1} passes ({dt1:.1f} s)"},
+            "host": host_cpu_record()}
 
 
 def cpu_baseline_spmm(A, X, rows=20000, target_s=10.0):
+    """The oracle's FP64 SpMM on the first `rows` rows, timed as cpu_baseline_spmv."""
     import oracle
     threads = oracle.max_threads()
     sel = np.arange(min(rows, A.nrows), dtype=np.int64)
     nnz_sel = int(A.indptr[sel[-1] + 1] - A.indptr[0])
-    t0 = time.perf_counter()
-    passes = 0
-    while time.perf_counter() - t0 < target_s:
-        oracle.spmm_rows(A, X, sel)
-        passes += 1
-    dt = time.perf_counter() - t0
     n = X.shape[1]
-    return {"value": round(2.0 * nnz_sel * n * passes / dt / 1e9, 3), "unit": "GFLOP/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"FP64 SpMM (n={n}) of the first {sel.size} rows, {passes} passes ({dt:.1f} s)"}
+    run = lambda: oracle.spmm_rows(A, X, sel)  # noqa: E731
+    g, passes, dt = _oracle_rate(run, 2.0 * nnz_sel * n, 0.6 * target_s)
+    oracle.set_threads(1)
+    try:
+        g1, passes1, dt1 = _oracle_rate(run, 2.0 * nnz_sel * n, 0.4 * target_s)
+    finally:
+        oracle.set_threads(threads)
+    return {"value": round(g, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 SpMM (n={n}) of the first {sel.size} rows, {passes} passes ({dt:.1f} s)",
+            "single_thread": {"value": round(g1, 3), "unit": "GFLOP/s", "cores": 1,
+                              "sample": f"{passes1} passes ({dt1:.1f} s)"},
+            "host": host_cpu_record()}
 
 
 def variant_kernel(v: int, far: int = 0) -> str:
