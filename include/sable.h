@@ -52,9 +52,13 @@ typedef enum {
 /* Extractor kinds (Sec. 3.2): band -> VDIA, block -> VBR, catch-all -> CSR. */
 enum { SABLE_X_VDIA = 1, SABLE_X_VBR = 2, SABLE_X_CSR = 3 };
 
-/* Block search variants: the literal recursive search of Alg. 1/2 ("paper"), allowed while
- * nrows * ncols * max(nrows, ncols) <= 2^37; a tiled delta-dense detection ("tiled") that
- * scales to any size; "auto" picks paper when it fits, else tiled. */
+/* Block search variants: the literal recursive search of Alg. 1/2 ("paper"), allowed when
+ * nrows * ncols * max(nrows, ncols) <= 2^37 or when its sparse window scan's work on the VBR
+ * extractor's input is <= 2^37 (one step per outer span (o0, o1) of length >= ceil(sqrt(
+ * amin_block)) of the row and column passes, plus min(inner length, entries of the span));
+ * a tiled delta-dense detection ("tiled") that scales to any size; "auto" picks paper when
+ * it is allowed, else tiled. A paper request for dimensions where even one step per span is
+ * over budget fails before any GPU work; otherwise the work is counted on the residual. */
 enum { SABLE_VBR_AUTO = 0, SABLE_VBR_PAPER = 1, SABLE_VBR_TILED = 2 };
 
 typedef struct {
@@ -88,7 +92,9 @@ typedef struct {
  *   coverage_pm     block coverage cutoff (Alg. 1; default 80 = 8%)
  *   tile_set_mask   tiled search: bit t selects tile size {4,6,8,16,32}[t]; 0 = all
  *   flags           SABLE_F_SPLIT_BF16 (default on): keep bf16 hi/lo copies of block values
- *                   for split-precision matrix-core SpMM. */
+ *                   for split-precision matrix-core SpMM; SABLE_F_SPARSE_SEARCH: run the
+ *                   literal block search's window scans over non-empty inner lines only (the
+ *                   same blocks; used anyway where the dense scan's tables would not fit). */
 typedef struct {
   int32_t delta_band_pm, delta_block_pm;
   int64_t amin_band, amin_block;
@@ -97,6 +103,7 @@ typedef struct {
 } sable_thresholds;
 
 #define SABLE_F_SPLIT_BF16 1u
+#define SABLE_F_SPARSE_SEARCH 2u
 
 typedef struct sable_plan_s* sable_plan_t;   /* opaque, library-owned */
 typedef struct sable_batch_s* sable_batch_t; /* opaque, library-owned */
@@ -124,6 +131,9 @@ typedef struct {
                               in a separate pass (see sable_spmv) */
   int64_t far_nnz;         /* CSR entries handled by that pass */
   double spec_ms;          /* wall time of sable_plan_specialize (0 if not specialized) */
+  uint64_t structure_hash; /* hash of A's sparsity pattern, the extractor list and the
+                              thresholds: plans with equal hashes have the same formats and
+                              schedules (the key of the autotuning cache) */
 } sable_plan_stats;
 
 /* Host buffers for sable_plan_export, sized from sable_plan_info:
@@ -132,7 +142,11 @@ typedef struct {
  *   blk[4*nblk] = (r0, r1, c0, c1) sorted by (r0, c0), blk_val_ptr[nblk], vbr_val[vbr_cells]
  *   (column-major within a block); csr_ptr[nrows+1], csr_col[csr_nnz], csr_val[csr_nnz];
  *   owner[nnz] (0 VDIA, 1 VBR, 2 CSR for every input entry) and slot[nnz] (its index in
- *   that format's value array). Any pointer may be NULL to skip that array. */
+ *   that format's value array); vbr_bf16[vbr_cells]: the split-bf16 copy that the
+ *   matrix-core SpMM multiplies, one 32-bit word hi | lo << 16 per block cell in the order of
+ *   vbr_val (hi = bf16 round-to-nearest-even of the value a, lo = the same rounding of
+ *   a - hi; all zero when the plan keeps no bf16 copies). Any pointer may be NULL to skip
+ *   that array. */
 typedef struct {
   float* vdia_val;
   int32_t* idiag;
@@ -149,6 +163,7 @@ typedef struct {
   float* csr_val;
   int8_t* owner;
   int64_t* slot;
+  uint32_t* vbr_bf16;
 } sable_partition_host;
 
 /* Fill *out with the defaults listed at sable_thresholds. */
@@ -186,7 +201,7 @@ sable_status sable_spmv(sable_plan_t p, const float* x, float* y, void* stream);
 
 /* Y = A X with n >= 1 right-hand sides (row-major, App. A.2). VBR blocks run on matrix
  * cores as split-bf16 products (hi*hi + hi*lo + lo*hi, fp32 accumulate) when the plan kept
- * bf16 copies (SABLE_F_SPLIT_BF16) and the selected SpMM variant uses them (0 or 3, see
+ * bf16 copies (SABLE_F_SPLIT_BF16) and the selected SpMM variant uses them (0, 3 or 4, see
  * sable_plan_set_variant), otherwise in fp32 on the vector units; VDIA and CSR run in fp32.
  * X and Y must be 16-byte aligned (SABLE_ERR_INVALID_ARG otherwise). */
 sable_status sable_spmm(sable_plan_t p, const float* X, float* Y, int32_t n, void* stream);
@@ -237,20 +252,36 @@ sable_status sable_update_values(sable_plan_t p, const float* values, void* stre
  * Time a small grid of launch parameters for the plan's fused kernel on `stream` (op 0 =
  * SpMV, 1 = SpMM with n columns) and keep the fastest. The SpMM choice is kept per n: later
  * sable_spmm calls with that n use it, other n use the most recent choice. x/X, y/Y are
- * scratch operands of the right sizes. Synchronises `stream`. */
+ * scratch operands of the right sizes. Synchronises `stream`.
+ * The grid: SpMV tile kernels (streamed tiles of 256/512/1024 rows, W lanes per CSR row,
+ * row-length bins mapped to subwave widths, non-temporal loads, the far-column split, the
+ * specialized kernel when present), the plain CSR baseline's kernels, and for SpMM the block
+ * path (matrix cores from registers or from LDS-staged panels, fp32 VALU) and the work split.
+ * Results are cached process-wide by (structure_hash, specialized or not, op, n, device): a
+ * plan with a pattern, extractor list and thresholds tuned before takes the stored choice at
+ * once, without timing anything. */
 sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, const float* x, float* y,
                             void* stream);
+
+/* Forget every cached autotuning result (the next sable_autotune times again). */
+sable_status sable_autotune_cache_clear(void);
 
 /* Select a fused-kernel variant explicitly (the set sable_autotune chooses from).
  * op 0 = hybrid SpMV: 0..2 streamed tiles of 256/512/1024 rows, 3..7 with 1/2/4/8/16 lanes
  *        per row on tiles of 256/W rows (bands lane per row; for W > 1 a row's lanes share its
  *        block columns and CSR entries), 8..10 = 0..2 with non-temporal matrix loads,
- *        11 = the run-time specialized kernel (after sable_plan_specialize);
+ *        11 = the run-time specialized kernel (after sable_plan_specialize), 12..14 = CSR
+ *        rows binned by length (0, 1-4, 5-8, 9-16, 17-32, 33-64, > 64 entries) within tiles of
+ *        up to 256 rows, each bin's rows taken by subwaves whose width gives about 1, 2 or 4
+ *        entries per lane (a wave for rows over 64 entries), bands and blocks lane per row;
  * op 1 = SpMM: 0 tiled with matrix-core blocks (for n <= 32 the four waves split the tile's
  *        row slices, otherwise its column chunks), 1 tiled fp32, 2 one wave per row, 3 tiled
- *        with matrix-core blocks and the column-chunk split at every n;
+ *        with matrix-core blocks and the column-chunk split at every n, 4 tiled with the
+ *        blocks on matrix cores from operands staged in LDS: per 64-row tile, the distinct
+ *        rows of X its blocks read are loaded once, 32 at a time, and multiplied in
+ *        16x16x32 bf16 steps;
  * op 2 = plain CSR baseline: 0..2 streamed, 3..9 with 1..64 lanes per row, 10..12 = 0..2
- *        with non-temporal matrix loads;
+ *        with non-temporal matrix loads, 13..15 = row-length bins as SpMV 12..14;
  * op 3 = far-column split of the streamed SpMV variants: 0 off, 1 on (when the plan has one).
  * Every variant computes the same product; each is bitwise reproducible on its own. An
  * explicit SpMM variant applies to every n (it clears the per-n autotuned choices). */

@@ -16,6 +16,7 @@ Functions (each follows the passage cited in oracle/sor.cpp):
                                  region; sparse = the window rule over non-empty inner
                                  indices only (same result, pinned against the dense scan)
   best_window(H, s, th, sparse)  the window scan of Alg. 2 for one span's inner counts
+  paper_fits(A, th)              the literal search's budget test and work count
   bf16_split(a)                  round-to-nearest-even hi/lo split of fp32 values
   rel_err(y, yref)               normwise relative error ||y - yref||_2 / ||yref||_2
 """
@@ -114,6 +115,8 @@ def _load():
     lib.sor_find_block_sparse.argtypes = lib.sor_find_block.argtypes
     lib.sor_find_block_sparse.restype = ctypes.c_int
     lib.sor_best_window.argtypes = [i64, P, i64, ctypes.POINTER(_Thr), ctypes.c_int32, P]
+    lib.sor_paper_fits.argtypes = [i64, i64, i64, P, P, ctypes.POINTER(_Thr), P]
+    lib.sor_paper_fits.restype = ctypes.c_int32
     lib.sor_bf16_split.argtypes = [i64, P, P, P]
     _lib = lib
     return lib
@@ -250,6 +253,20 @@ def best_window(H, s: int, th: Thresholds | None = None, sparse: bool = False):
     cth = th._c()
     lib.sor_best_window(H.size, _p(H), int(s), ctypes.byref(cth), 1 if sparse else 0, _p(out))
     return tuple(int(t) for t in out)
+
+
+def paper_fits(A, th: Thresholds | None = None):
+    """The literal block search's budget test on A: (allowed, work count). Allowed when
+    nrows * ncols * max(nrows, ncols) <= 2^37, or when the sparse scan's work, one step per
+    outer span of both passes plus min(inner length, the span's entries), is <= 2^37."""
+    lib = _load()
+    th = th or Thresholds()
+    ip, ix, _ = _csr_arrays(A)
+    cost = np.zeros(1, np.int64)
+    cth = th._c()
+    ok = lib.sor_paper_fits(A.nrows, A.ncols, int(ip[-1]), _p(ip), _p(ix), ctypes.byref(cth),
+                            _p(cost))
+    return bool(ok), int(cost[0])
 
 
 def partition_spmv_from_export(P: dict, x: np.ndarray) -> np.ndarray:

@@ -501,6 +501,7 @@ struct PaperState {
   const Mat* R;
   const Csc* C;
   const Thr* th;
+  bool sparse = false;  // window scans over non-empty inner indices (equal results)
   std::vector<char> used_r, used_c;
   std::vector<Blk> out;
 };
@@ -510,8 +511,10 @@ void decompose(PaperState& st, Blk reg) {
   const Thr& th = *st.th;
   if (reg.r1 <= reg.r0 || reg.c1 <= reg.c0) return;
   if ((reg.r1 - reg.r0) * (reg.c1 - reg.c0) < th.amin_block) return;
-  Cand b = find_block(*st.R, *st.C, reg, true, th);
-  Cand b2 = find_block(*st.R, *st.C, reg, false, th);
+  Cand b = st.sparse ? find_block_sparse(*st.R, *st.C, reg, true, th)
+                     : find_block(*st.R, *st.C, reg, true, th);
+  Cand b2 = st.sparse ? find_block_sparse(*st.R, *st.C, reg, false, th)
+                      : find_block(*st.R, *st.C, reg, false, th);
   bool use_csc = score_gt(b2.nnz, b2.area, b.nnz, b.area);
   Cand bc = use_csc ? b2 : b;
   if (bc.nnz < 0 || bc.area < th.amin_block) return;
@@ -531,7 +534,43 @@ void decompose(PaperState& st, Blk reg) {
   decompose(st, {B.r0, B.r1, B.c1, reg.c1});
 }
 
-bool paper_mode_fits(i64 nrows, i64 ncols) {
+// Work of the literal block search on a matrix, counted per (o0, o1) span of both passes of
+// the top-level FindBlock: one step per span plus one per non-empty inner index it can see,
+// bounded by min(inner length, entries of the span). cnt[o] = entries of outer slice o.
+// Stops counting once the total passes `limit`.
+u128 pass_cost(const std::vector<i64>& cnt, i64 Lin, i64 smin, u128 limit) {
+  const i64 n = (i64)cnt.size();
+  u128 total = 0;
+  for (i64 o0 = 0; o0 < n && total <= limit; ++o0) {
+    i64 N = 0;  // entries of outer slices o0 .. o1
+    for (i64 o1 = o0; o1 < n; ++o1) {
+      N += cnt[o1];
+      if (o1 - o0 + 1 >= smin) total += 1 + (u128)std::min(Lin, N);
+    }
+  }
+  return total;
+}
+
+// Budget of the literal search (Alg. 1 / Alg. 2 on the VBR extractor's input): allowed when
+// nrows * ncols * max(nrows, ncols) <= 2^37 (the dense scan's bound), or when the sparse
+// scan's work on this residual, pass_cost over rows plus over columns, is <= 2^37.
+bool paper_mode_fits(const Mat& R, const Thr& th) {
+  const u128 m = (u128)std::max(R.nrows, R.ncols);
+  if ((u128)R.nrows * (u128)R.ncols * m <= ((u128)1 << 37)) return true;
+  std::vector<i64> rc(R.nrows, 0), cc(R.ncols, 0);
+  for (i64 i = 0; i < R.nrows; ++i) {
+    rc[i] = R.ptr[i + 1] - R.ptr[i];
+    for (i64 k = R.ptr[i]; k < R.ptr[i + 1]; ++k) cc[R.col[k]] += 1;
+  }
+  const i64 smin = ceil_sqrt(th.amin_block);
+  const u128 lim = (u128)1 << 37;
+  auto pairs = [&](i64 n) { const u128 k = n >= smin ? (u128)(n - smin + 1) : 0; return k * (k + 1) / 2; };
+  if (pairs(R.nrows) + pairs(R.ncols) > lim) return false;  // one step per span already exceeds
+  const u128 rows = pass_cost(rc, R.ncols, smin, lim);
+  return rows <= lim && rows + pass_cost(cc, R.nrows, smin, lim - rows) <= lim;
+}
+
+bool dims_fit(i64 nrows, i64 ncols) {
   const u128 m = (u128)std::max(nrows, ncols);
   return (u128)nrows * (u128)ncols * m <= ((u128)1 << 37);
 }
@@ -540,6 +579,7 @@ std::vector<Blk> extract_blocks_paper(const Mat& R, const Thr& th) {
   Csc C = transpose(R);
   PaperState st;
   st.R = &R; st.C = &C; st.th = &th;
+  st.sparse = !dims_fit(R.nrows, R.ncols);
   st.used_r.assign(R.nrows, 0);
   st.used_c.assign(R.ncols, 0);
   decompose(st, {0, R.nrows, 0, R.ncols});
@@ -672,8 +712,8 @@ int build_plan(i64 nrows, i64 ncols, i64 nnz, const i64* indptr, const int32_t* 
       }
     } else if (kinds[e] == K_VBR) {
       int mode = modes[e];
-      if (mode == 0) mode = paper_mode_fits(nrows, ncols) ? 1 : 2;
-      if (mode == 1 && !paper_mode_fits(nrows, ncols)) return 4;
+      if (mode == 0) mode = paper_mode_fits(R, th) ? 1 : 2;
+      if (mode == 1 && !paper_mode_fits(R, th)) return 4;
       std::vector<Blk> B;
       int32_t T = 0;
       if (mode == 1) B = extract_blocks_paper(R, th);
@@ -805,6 +845,27 @@ void sor_best_window(int64_t Lin, const int64_t* H, int64_t s, const Thr* th, in
     best_window(std::vector<i64>(H, H + Lin), s, *th, 0, 0, best);
   }
   out[0] = best.nnz; out[1] = best.area; out[2] = best.i0; out[3] = best.i1;
+}
+
+// The literal search's budget test on a matrix (1 = allowed) and its work count (capped at
+// 2^62), for pins.
+int32_t sor_paper_fits(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* indptr,
+                       const int32_t* indices, const Thr* th, int64_t* cost) {
+  Mat R;
+  R.nrows = nrows;
+  R.ncols = ncols;
+  R.ptr.assign(indptr, indptr + nrows + 1);
+  R.col.assign(indices, indices + nnz);
+  std::vector<i64> rc(nrows, 0), cc(ncols, 0);
+  for (i64 i = 0; i < nrows; ++i) {
+    rc[i] = R.ptr[i + 1] - R.ptr[i];
+    for (i64 k = R.ptr[i]; k < R.ptr[i + 1]; ++k) cc[R.col[k]] += 1;
+  }
+  const i64 smin = ceil_sqrt(th->amin_block);
+  const u128 cap = (u128)1 << 62;
+  const u128 c = pass_cost(rc, ncols, smin, cap) + pass_cost(cc, nrows, smin, cap);
+  *cost = (int64_t)std::min(c, cap);
+  return paper_mode_fits(R, *th) ? 1 : 0;
 }
 
 // The same pass through the sparse window scan (find_block_sparse).

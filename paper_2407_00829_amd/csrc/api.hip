@@ -9,7 +9,7 @@
 namespace sable {
 
 const char* last_error();
-bool vbr_paper_fits(i64 nrows, i64 ncols);
+bool vbr_paper_fits(i64 nrows, i64 ncols, i64 amin);
 
 namespace {
 
@@ -127,9 +127,59 @@ double* scratch_for_current_device() {
   return g_scratch_ptr[dev];
 }
 
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {  // splitmix64 finaliser
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// sum over k of mix(k, a[k]) mod 2^64 (order-independent, so the atomic sum is exact)
+__global__ void k_hash_i32(const int32_t* __restrict__ a, i64 n, uint64_t salt,
+                           unsigned long long* __restrict__ out) {
+  uint64_t acc = 0;
+  for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x)
+    acc += mix64(((uint64_t)k << 32) ^ (uint32_t)a[k] ^ salt);
+  atomicAdd(out, (unsigned long long)acc);
+}
+
+uint64_t mix64_host(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Hash of everything the plan's structure depends on: the sparsity pattern of A, the
+// extractor list and the thresholds (not the values). Plans with equal hashes have the same
+// formats and schedules, so one autotuning result serves all of them.
+uint64_t structure_hash(const sable_csr& A, const sable_extractor* list, int nlist,
+                        const sable_thresholds& th, hipStream_t s) {
+  DBuf<unsigned long long> d(2);
+  HIPC(hipMemsetAsync(d.p, 0, 2 * sizeof(unsigned long long), s));
+  k_hash_i32<<<grid_for((i64)A.nrows + 1, 256), 256, 0, s>>>(A.indptr, (i64)A.nrows + 1, 0x9e3779b97f4a7c15ull, d.p);
+  LAUNCH_CHECK();
+  if (A.nnz) {
+    k_hash_i32<<<grid_for(A.nnz, 256), 256, 0, s>>>(A.indices, A.nnz, 0x7f4a7c159e3779b9ull, d.p + 1);
+    LAUNCH_CHECK();
+  }
+  unsigned long long h2[2];
+  HIPC(hipMemcpyAsync(h2, d.p, sizeof(h2), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  uint64_t h = mix64_host(h2[0]) ^ mix64_host(h2[1] + 0x632be59bd9b4e019ull);
+  auto put = [&](uint64_t v) { h = mix64_host(h ^ v) + 0x9e3779b97f4a7c15ull; };
+  put((uint64_t)(uint32_t)A.nrows); put((uint64_t)(uint32_t)A.ncols); put((uint64_t)A.nnz);
+  for (int e = 0; e < nlist; ++e) put(((uint64_t)(uint32_t)list[e].kind << 32) | (uint32_t)list[e].vbr_mode);
+  put((uint64_t)(uint32_t)th.delta_band_pm << 32 | (uint32_t)th.delta_block_pm);
+  put((uint64_t)th.amin_band); put((uint64_t)th.amin_block);
+  put((uint64_t)(uint32_t)th.lseg << 32 | (uint32_t)th.wmax);
+  put((uint64_t)(uint32_t)th.dmax << 32 | (uint32_t)th.coverage_pm);
+  put((uint64_t)(uint32_t)th.tile_set_mask << 32 | th.flags);
+  return h;
+}
+
 void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list, int nlist,
                 const sable_thresholds& th, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
+  P.structure_hash = structure_hash(A, list, nlist, th, s);
   P.nrows = A.nrows;
   P.ncols = A.ncols;
   P.nnz = A.nnz;
@@ -175,7 +225,10 @@ void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list
       build_schedule(P, P.sched[k], 256 << k, true, s, false, true);
       build_schedule(P, P.sched_plain[k], 256 << k, false, s, false, true);
     }
+    build_bins(P, P.sched[0], true, s);
+    build_bins(P, P.sched_plain[0], false, s);
     build_schedule(P, P.sched_mm, 64, true, s, true);
+    build_mm_panels(P, s);
     for (int k = 0; k < 4; ++k) build_schedule(P, P.sched_w[k], 128 >> k, true, s);
     build_far_split(P, s);
   }
@@ -214,8 +267,10 @@ sable::i64 sable_plan_s::device_bytes() const {
     const sable::Schedule* S = k < 3 ? &sched[k] : k < 6 ? &sched_plain[k - 3] : k == 6 ? &sched_mm
                                                                                        : &sched_w[k - 7];
     b += S->tile_seg_lo.bytes() + S->tile_seg_hi.bytes() + S->tile_blk_ptr.bytes() +
-         S->tile_blk.bytes() + S->order.bytes() + S->row0.bytes();
+         S->tile_blk.bytes() + S->order.bytes() + S->row0.bytes() + S->bin_rows.bytes() +
+         S->bin_off.bytes();
   }
+  b += mm_panels.kcol.bytes() + mm_panels.kptr.bytes() + mm_panels.bpos.bytes();
   b += far.ccol.bytes() + far.far_col.bytes() + far.far_src.bytes() + far.far_val.bytes() +
        far.far_prod.bytes() + far.far_val64.bytes() + far.far_prod64.bytes() + far.chunk.bytes();
   return b;
@@ -266,14 +321,16 @@ sable_status sable_plan(const sable_csr* A, const sable_extractor* list, int32_t
       if (list[e].kind == SABLE_X_VBR) {
         const int m = list[e].vbr_mode;
         if (m < 0 || m > 2) SB_THROW(SABLE_ERR_INVALID_ARG, "vbr_mode %d", m);
-        if (m == SABLE_VBR_PAPER && !vbr_paper_fits(A->nrows, A->ncols))
-          SB_THROW(SABLE_ERR_TOO_LARGE, "literal block search over budget for %dx%d", A->nrows,
-                   A->ncols);
       }
     }
     sable_thresholds th;
     sable_thresholds_default(&th);
     if (th_in) th = *th_in;
+    for (int e = 0; e < nlist - 1; ++e)
+      if (list[e].kind == SABLE_X_VBR && list[e].vbr_mode == SABLE_VBR_PAPER &&
+          !vbr_paper_fits(A->nrows, A->ncols, std::max<i64>(1, th.amin_block)))
+        SB_THROW(SABLE_ERR_TOO_LARGE, "literal block search over budget for %dx%d", A->nrows,
+                 A->ncols);
     if (th.delta_block_pm < 500 || th.delta_block_pm > 1000 || th.delta_band_pm < 1 ||
         th.delta_band_pm > 1000 || th.amin_block < 1 || th.amin_band < 1 || th.lseg < 1 ||
         th.wmax < 0 || th.wmax > 63 || th.coverage_pm < 0 || th.coverage_pm > 1000 || th.tile_set_mask < 0 ||
@@ -323,6 +380,7 @@ sable_status sable_plan_info(sable_plan_t p, sable_plan_stats* o) {
     o->bytes_matrix = 4 * p->vdia_cells + 20 * (i64)p->nseg + 4 * p->vbr_cells +
                       8 * p->csr_nnz + 4 * ((i64)p->nrows + 1);
     o->device_bytes = p->device_bytes();
+    o->structure_hash = p->structure_hash;
     o->plan_ms = p->plan_ms;
     o->spmv_variant = p->prm.spmv_variant;
     o->spmm_variant = p->prm.spmm_mode;
@@ -358,6 +416,26 @@ sable_status sable_plan_export(sable_plan_t p, const sable_partition_host* o) {
       std::vector<int32_t> h(p->nrows + 1);
       HIPC(hipMemcpy(h.data(), p->csr_ptr.p, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
       for (size_t i = 0; i < h.size(); ++i) o->csr_ptr[i] = h[i];
+    }
+    if (o->vbr_bf16 && p->vbr_cells) {
+      // the device copy is row-major per block with the row stride padded to a multiple of 4;
+      // the export follows vbr_val's column-major order
+      std::fill(o->vbr_bf16, o->vbr_bf16 + p->vbr_cells, 0u);
+      if (p->vbr_mma.p) {
+        std::vector<int32_t> blk;
+        std::vector<i64> vp, mp;
+        std::vector<uint32_t> w;
+        to_host(blk, p->blk.p, 4 * (size_t)p->nblk, nullptr);
+        to_host(vp, p->blk_val_ptr.p, p->nblk, nullptr);
+        to_host(mp, p->blk_mma_ptr.p, p->nblk, nullptr);
+        to_host(w, p->vbr_mma.p, p->vbr_mma.n, nullptr);
+        for (int b = 0; b < p->nblk; ++b) {
+          const i64 h = blk[4 * b + 1] - blk[4 * b], wd = blk[4 * b + 3] - blk[4 * b + 2];
+          const i64 w4 = (wd + 3) & ~(i64)3;
+          for (i64 r = 0; r < h; ++r)
+            for (i64 k = 0; k < wd; ++k) o->vbr_bf16[vp[b] + k * h + r] = w[mp[b] + r * w4 + k];
+        }
+      }
     }
   });
 }

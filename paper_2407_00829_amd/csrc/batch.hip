@@ -5,14 +5,14 @@
 // resident workgroups, pull units from their own atomic counter; a unit runs exactly the tile
 // body of the standalone product, so each item's result is bitwise equal to its standalone
 // launch with the same kernel (SpMV: the 256-row streamed tile, variant 0; SpMM: the fused
-// tile in the plan's matrix-core mode). Keeping the two apart lets each run at the occupancy
+// tile in the plan's matrix-core mode, the LDS-staged panel tile included). Keeping the two apart lets each run at the occupancy
 // of its standalone kernel. The last unit of an item stamps the GPU wall clock. A reset kernel
 // (no memset nodes) clears the counters and stamps the batch start; the three kernels are
 // captured once and replayed.
 #include <algorithm>
 
 #include "exec.h"
-#include "spmm_tile.h"
+#include "spmm_panel.h"
 
 namespace sable {
 
@@ -44,6 +44,7 @@ __global__ void k_batch_reset(unsigned* __restrict__ counter, unsigned* __restri
 
 constexpr int kBatchSpmvLds = kCsrChunk + kSpmvThreads;  // spmv_tile_stream<1>
 constexpr int kBatchSpmmLds = kMmRows * kMmCols + kMmBlkStage * kBlkDesc;
+static_assert(kBatchSpmmLds * 4 >= kPanLdsBytes, "the panel tile fits the SpMM units' LDS");
 
 // Units of one list: list[k] is the item of the k-th entry, off[k] its first unit.
 template <int OP>
@@ -79,7 +80,8 @@ __device__ __forceinline__ void batch_units(const PlanView* __restrict__ views,
       int rt = local % I.units_per_col;
       const int cc = local / I.units_per_col;
       if (P.tile_order) rt = P.tile_order[rt];
-      spmm_tile(P, rt * kMmRows, cc * kMmCols, I.n, I.x, I.y, lds, I.mfma);
+      if (I.mfma == 3) spmm_tile_panel(P, rt, cc * kMmCols, I.n, I.x, I.y, reinterpret_cast<uint8_t*>(lds));
+      else spmm_tile(P, rt * kMmRows, cc * kMmCols, I.n, I.x, I.y, lds, I.mfma);
     }
     __syncthreads();
     // completion count only: nothing in the kernel reads another unit's output, so no
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(256, 3) void k_batch_spmm(const PlanView* __restric
                                                        i64 total, unsigned* __restrict__ counter,
                                                        unsigned* __restrict__ done,
                                                        unsigned long long* __restrict__ stamps) {
-  __shared__ float lds[kBatchSpmmLds];  // 40 KB
+  __shared__ __align__(16) float lds[kBatchSpmmLds];  // 40 KB
   batch_units<1>(views, items, list, off, nlist, total, counter, done, stamps, lds);
 }
 

@@ -39,6 +39,10 @@ struct PlanView {
   // whose product far_prod[q] the gather pass has already computed
   const float* far_prod;
   const double* far_prod64;  // the same for the fp64 executor
+  // matrix-core SpMM panels of the 64-row SpMM schedule (null without them)
+  const int32_t* mm_kcol;
+  const int32_t* mm_kptr;
+  const int32_t* mm_bpos;
 };
 
 // Value arrays of the view for the executor's value type.
@@ -395,6 +399,89 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
   for (int q = 0; q < RPT; ++q) {
     const int r = r0 + t + kSpmvThreads * q;
     if (r < rend) y[r] = acc[q] + cs[q];
+  }
+}
+
+// ---- SpMV tile body, row-length bins ----------------------------------------------------
+// Rows of the CSR part are binned by length: 0, 1-4, 5-8, 9-16, 17-32, 33-64, > 64 entries
+// (bins 0..6). The plan keeps, per tile, its rows grouped by bin (stable) and the bin
+// boundaries. 256 threads over a tile of up to 256 rows:
+//  1. bands and blocks lane per row (as the W = 1 tile body); a row without CSR entries is
+//     stored at once, the others leave their partial in LDS;
+//  2. bin by bin, each row of the bin is taken by a subwave of kBinWidth[u][bin] lanes
+//     (u = the plan's entries-per-lane setting: about 1, 2 or 4 entries per lane), the
+//     lanes stride over the row's entries and an xor tree adds their sums.
+// Per row: y = (bands + blocks) + CSR (lane partials in index-strided order, xor tree).
+constexpr int kNumBins = 7;
+__host__ __device__ __forceinline__ int csr_bin(int len) {
+  return len == 0 ? 0 : len <= 4 ? 1 : len <= 8 ? 2 : len <= 16 ? 3 : len <= 32 ? 4 : len <= 64 ? 5 : 6;
+}
+// lanes per row of each bin for 1, 2 and 4 entries per lane (bin 0 unused)
+__host__ __device__ __forceinline__ int bin_width(int u, int bin) {
+  const int maxlen = bin >= 6 ? 256 : 2 << bin;  // 4, 8, 16, 32, 64; long rows get a wave
+  int w = maxlen >> u;                            // u = log2(entries per lane)
+  return w < 1 ? 1 : w > 64 ? 64 : w;
+}
+
+__device__ __forceinline__ void spmv_tile_binned(const PlanView& P, int tile, const int32_t* __restrict__ brow,
+                                                 const int32_t* __restrict__ boff, int u,
+                                                 const float* __restrict__ x, float* __restrict__ y,
+                                                 float* __restrict__ part) {
+  int r0, rend;
+  tile_rows(P, tile, r0, rend);
+  const int t = threadIdx.x;
+  const int r = r0 + t;
+  const bool act = r < rend;
+  int kb = 0, ke = 0;
+  if (act) {
+    kb = P.csr_ptr[r];
+    ke = P.csr_ptr[r + 1];
+  }
+  float acc = 0.f;
+  const int slo = P.tile_seg_lo[tile], shi = P.tile_seg_hi[tile];
+  for (int s = slo; s < shi; ++s) {
+    const int rs = P.seg_row_start[s], nr = P.seg_nrows[s];
+    if (act && r >= rs && r < rs + nr) {
+      const int nd = P.seg_ndiags[s];
+      const int32_t* od = P.idiag + P.seg_idiag_ptr[s];
+      const float* v = P.vdia_val + P.seg_val_ptr[s] + (r - rs);
+      for (int d = 0; d < nd; ++d) {
+        const int c = r + od[d];
+        if ((unsigned)c < (unsigned)P.ncols) acc += v[(i64)d * nr] * x[c];
+      }
+    }
+  }
+  for (int q = P.tile_blk_ptr[tile]; q < P.tile_blk_ptr[tile + 1]; ++q) {
+    const int b = P.tile_blk[q];
+    const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
+    if (act && r >= br0 && r < br1) {
+      const int c0 = P.blk[4 * b + 2], c1 = P.blk[4 * b + 3];
+      const float* v = P.vbr_val + P.blk_val_ptr[b] + (r - br0);
+      for (int c = c0; c < c1; ++c) acc += v[(i64)(c - c0) * (br1 - br0)] * x[c];
+    }
+  }
+  if (act) {
+    if (ke == kb) y[r] = acc;
+    else part[t] = acc;
+  }
+  __syncthreads();
+  const int* off = boff + (i64)tile * (kNumBins + 1);
+  for (int bin = 1; bin < kNumBins; ++bin) {
+    const int pa = off[bin], pz = off[bin + 1];
+    if (pa >= pz) continue;
+    const int W = bin_width(u, bin);
+    const int lane = t & (W - 1), grp = t / W, ngrp = kSpmvThreads / W;
+    for (int pos = pa + grp; pos - grp < pz; pos += ngrp) {  // whole subwaves iterate together
+      const bool on = pos < pz;
+      const int rr = on ? brow[pos] : r0;
+      float cs = 0.f;
+      if (on) {
+        const int e1 = P.csr_ptr[rr + 1];
+        for (int k = P.csr_ptr[rr] + lane; k < e1; k += W) cs += P.csr_val[k] * x[P.csr_col[k]];
+      }
+      for (int o = W >> 1; o > 0; o >>= 1) cs += __shfl_xor(cs, o);
+      if (on && lane == 0) y[rr] = part[rr - r0] + cs;
+    }
   }
 }
 

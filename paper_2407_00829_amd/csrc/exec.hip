@@ -2,7 +2,7 @@
 #include <algorithm>
 
 #include "exec.h"
-#include "spmm_tile.h"
+#include "spmm_panel.h"
 
 namespace sable {
 
@@ -48,6 +48,11 @@ PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool fa
   v.csr_ptr = P.csr_ptr.p;
   v.csr_col = P.csr_col.p;
   v.csr_val = P.csr_val.p;
+  if (&S == &P.sched_mm && P.mm_panels.kptr.p) {
+    v.mm_kcol = P.mm_panels.kcol.p;
+    v.mm_kptr = P.mm_panels.kptr.p;
+    v.mm_bpos = P.mm_panels.bpos.p;
+  }
   if (far && P.far.npanel && P.prm.far_split) {
     v.csr_col = P.far.ccol.p;
     v.far_prod = P.far.far_prod.p;
@@ -220,6 +225,30 @@ __global__ __launch_bounds__(256) void k_spmv_stream(PlanView P, const float* __
   spmv_tile_stream<RPT, NT>(P, tile, x, y, lds);
 }
 
+// Row-length bins: subwave widths per bin (u = log2 of entries per lane).
+__global__ __launch_bounds__(256) void k_spmv_binned(PlanView P, const int32_t* __restrict__ brow,
+                                                    const int32_t* __restrict__ boff, int u,
+                                                    const float* __restrict__ x,
+                                                    float* __restrict__ y) {
+  __shared__ float part[kSpmvThreads];
+  int tile = xcd_tile(blockIdx.x, P.ntiles);
+  if (tile >= P.ntiles) return;
+  if (P.tile_order) tile = P.tile_order[tile];
+  spmv_tile_binned(P, tile, brow, boff, u, x, y, part);
+}
+
+// The plain CSR baseline's binned variants (the same body over the input as one CSR matrix).
+__global__ __launch_bounds__(256) void k_csr_binned(PlanView P, const int32_t* __restrict__ brow,
+                                                   const int32_t* __restrict__ boff, int u,
+                                                   const float* __restrict__ x,
+                                                   float* __restrict__ y) {
+  __shared__ float part[kSpmvThreads];
+  int tile = xcd_tile(blockIdx.x, P.ntiles);
+  if (tile >= P.ntiles) return;
+  if (P.tile_order) tile = P.tile_order[tile];
+  spmv_tile_binned(P, tile, brow, boff, u, x, y, part);
+}
+
 // Far-column gather: workgroup b runs on XCD b mod 8 and takes that XCD's (b / 8)-th work
 // item (begin, end, panel); it stages the panel's x slice in LDS with coalesced loads, then
 // multiplies its entries by x values read from LDS.
@@ -325,6 +354,17 @@ __global__ __launch_bounds__(kMmThreads, 4) void k_spmm_tile_valu(PlanView P, co
   if (t >= ntile) return;
   if (P.tile_order) t = P.tile_order[t];
   spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, 0);
+}
+
+// Blocks on matrix cores from LDS-staged panels (16x16x32 bf16 steps).
+__global__ __launch_bounds__(kMmThreads, 4) void k_spmm_panel(PlanView P, const float* __restrict__ X,
+                                                          float* __restrict__ Y, int n) {
+  __shared__ __align__(16) uint8_t lds[kPanLdsBytes];
+  const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
+  int t = xcd_tile(blockIdx.x, ntile);
+  if (t >= ntile) return;
+  if (P.tile_order) t = P.tile_order[t];
+  spmm_tile_panel(P, t, blockIdx.y * kMmCols, n, X, Y, lds);
 }
 
 // FP64 executor: the same streamed SpMV tile body and SpMM tile (blocks on the VALU) over the
@@ -565,6 +605,14 @@ void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s)
     launch_spmv_spec(P, x, y, s);
     return;
   }
+  if (var >= 12) {
+    const Schedule& S = P.sched[0];
+    const PlanView v = make_view(P, S, false);
+    const unsigned nb = (unsigned)(((v.ntiles + 7) / 8) * 8);
+    k_spmv_binned<<<nb, kSpmvThreads, 0, s>>>(v, S.bin_rows.p, S.bin_off.p, var - 12, x, y);
+    LAUNCH_CHECK();
+    return;
+  }
   if (var <= 2 || var >= 8) {
     const int k = var <= 2 ? var : var - 8;
     const PlanView v = make_view(P, P.sched[k], false, true);
@@ -592,6 +640,14 @@ void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s)
 
 void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
   const int var = P.prm.plain_variant;
+  if (var >= 13) {
+    const Schedule& S = P.sched_plain[0];
+    const PlanView v = make_view(P, S, true);
+    const unsigned nb = (unsigned)(((v.ntiles + 7) / 8) * 8);
+    k_csr_binned<<<nb, kSpmvThreads, 0, s>>>(v, S.bin_rows.p, S.bin_off.p, var - 13, x, y);
+    LAUNCH_CHECK();
+    return;
+  }
   if (var <= 2 || var >= 10) {
     const int k = var <= 2 ? var : var - 10;
     launch_k_csr_stream(make_view(P, P.sched_plain[k], true), 1 << k, var >= 10, x, y, s);
@@ -613,8 +669,73 @@ void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStrea
 }
 
 int spmm_mfma_mode(const sable_plan_s& P, int mode) {
+  // the panel tile also serves plans without blocks (bands and CSR only)
+  if (mode == 4) return P.nblk == 0 || P.mm_panels.kptr.p ? 3 : 0;
   if (!P.vbr_mma.p || P.nblk == 0) return 0;
   return mode == 0 ? 1 : mode == 3 ? 2 : 0;
+}
+
+void build_bins(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s) {
+  S.bin_rows.reset();
+  S.bin_off.reset();
+  if (S.ntiles == 0 || S.rows_per_tile > kSpmvThreads) return;
+  std::vector<int32_t> ptr, row0;
+  to_host(ptr, with_formats ? P.csr_ptr.p : P.a_ptr.p, (size_t)P.nrows + 1, s);
+  if (S.row0.p) to_host(row0, S.row0.p, (size_t)S.ntiles + 1, s);
+  std::vector<int32_t> rows(P.nrows), off((size_t)S.ntiles * (kNumBins + 1));
+  int at = 0;
+  for (int t = 0; t < S.ntiles; ++t) {
+    const int a = S.row0.p ? row0[t] : t * S.rows_per_tile;
+    const int b = S.row0.p ? row0[t + 1] : std::min(P.nrows, (t + 1) * S.rows_per_tile);
+    int cnt[kNumBins] = {0};
+    for (int r = a; r < b; ++r) cnt[csr_bin(ptr[r + 1] - ptr[r])]++;
+    int* o = off.data() + (size_t)t * (kNumBins + 1);
+    o[0] = at;
+    for (int k = 0; k < kNumBins; ++k) o[k + 1] = o[k] + cnt[k];
+    int fill[kNumBins];
+    for (int k = 0; k < kNumBins; ++k) fill[k] = o[k];
+    for (int r = a; r < b; ++r) rows[fill[csr_bin(ptr[r + 1] - ptr[r])]++] = r;
+    at = o[kNumBins];
+  }
+  to_dev(S.bin_rows, rows, s);
+  to_dev(S.bin_off, off, s);
+  HIPC(hipStreamSynchronize(s));
+}
+
+void build_mm_panels(sable_plan_s& P, hipStream_t s) {
+  MmPanels& M = P.mm_panels;
+  M.kcol.reset();
+  M.kptr.reset();
+  M.bpos.reset();
+  const Schedule& S = P.sched_mm;
+  if (!P.vbr_mma.p || P.nblk == 0 || S.ntiles == 0) return;
+  std::vector<int32_t> blk, tptr, tblk;
+  to_host(blk, P.blk.p, 4 * (size_t)P.nblk, s);
+  to_host(tptr, S.tile_blk_ptr.p, (size_t)S.ntiles + 1, s);
+  to_host(tblk, S.tile_blk.p, (size_t)tptr[S.ntiles], s);
+  std::vector<int32_t> kcol, kptr(S.ntiles + 1), bpos(tblk.size());
+  kptr[0] = 0;
+  for (int t = 0; t < S.ntiles; ++t) {
+    // the tile's blocks are listed by first column: one sweep gives the distinct columns
+    const size_t base = kcol.size();
+    int covered = INT32_MIN;  // every column below this is listed already
+    for (int q = tptr[t]; q < tptr[t + 1]; ++q) {
+      const int c0 = blk[4 * tblk[q] + 2], c1 = blk[4 * tblk[q] + 3];
+      for (int c = std::max(c0, covered); c < c1; ++c) kcol.push_back(c);
+      covered = std::max(covered, c1);
+    }
+    for (int q = tptr[t]; q < tptr[t + 1]; ++q) {
+      const int c0 = blk[4 * tblk[q] + 2];
+      bpos[q] = (int32_t)(std::lower_bound(kcol.begin() + base, kcol.end(), c0) - (kcol.begin() + base));
+    }
+    while ((kcol.size() - base) % kPanK) kcol.push_back(-1);
+    if (kcol.size() > (size_t)INT32_MAX) SB_THROW(SABLE_ERR_TOO_LARGE, "panel list too long");
+    kptr[t + 1] = (int32_t)kcol.size();
+  }
+  to_dev(M.kcol, kcol, s);
+  to_dev(M.kptr, kptr, s);
+  to_dev(M.bpos, bpos, s);
+  HIPC(hipStreamSynchronize(s));
 }
 
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s) {
@@ -627,7 +748,8 @@ void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStre
     const int ntile = (P.nrows + kMmRows - 1) / kMmRows;
     dim3 grid((unsigned)(((ntile + 7) / 8) * 8), (unsigned)((n + kMmCols - 1) / kMmCols));
     const int mfma = spmm_mfma_mode(P, mode);
-    if (mfma) k_spmm_tile<<<grid, kMmThreads, 0, s>>>(v, X, Y, n, mfma);
+    if (mfma == 3) k_spmm_panel<<<grid, kMmThreads, 0, s>>>(v, X, Y, n);
+    else if (mfma) k_spmm_tile<<<grid, kMmThreads, 0, s>>>(v, X, Y, n, mfma);
     else k_spmm_tile_valu<<<grid, kMmThreads, 0, s>>>(v, X, Y, n);
   }
   LAUNCH_CHECK();
@@ -636,7 +758,7 @@ void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStre
 void launch_spmv_f64(const sable_plan_s& P, const double* x, double* y, hipStream_t s) {
   // the streamed variant's tile size (rows per thread) if one is selected, else 1
   const int var = P.prm.spmv_variant;
-  const int k = var <= 2 ? var : var >= 8 ? var - 8 : 0;
+  const int k = var <= 2 ? var : (var >= 8 && var <= 10) ? var - 8 : 0;
   const PlanView v = make_view(P, P.sched[k], false, P.far.far_prod64.p != nullptr);
   if (v.far_prod64) {  // far-column products first, as in the fp32 path
     k_far_gather<double><<<(unsigned)(8 * P.far.per_xcd), kFarThreads, 0, s>>>(

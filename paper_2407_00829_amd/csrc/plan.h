@@ -29,13 +29,16 @@ struct BlkRec {  // block rectangle rows [r0, r1), columns [c0, c1)
 // Launch parameters of the fused kernels (autotuned).
 // SpMV kernel variants: 0..2 = streamed tile body with 1, 2, 4 rows per thread (tiles of
 // 256, 512, 1024 rows); 3..7 = row-per-lane bands/blocks with 1, 2, 4, 8, 16 lanes per CSR
-// row (tiles of 256 / W rows); 8..10 = 0..2 with non-temporal matrix loads. The plain CSR
-// baseline: 0..2 streamed, 3..9 = 1..64 lanes per row, 10..12 = 0..2 non-temporal.
+// row (tiles of 256 / W rows); 8..10 = 0..2 with non-temporal matrix loads; 11 = run-time
+// specialized; 12..14 = row-length bins with subwave widths for about 1, 2, 4 entries per
+// lane. The plain CSR baseline: 0..2 streamed, 3..9 = 1..64 lanes per row, 10..12 = 0..2
+// non-temporal, 13..15 = row-length bins as 12..14.
 struct ExecParams {
   int spmv_variant = 1;
   int plain_variant = 1;
   int spmm_mode = 0;  // fused SpMM variant: 0 tiled, matrix cores (automatic work split),
-                      // 1 tiled fp32 VALU, 2 wave per row, 3 tiled, matrix cores (chunk split)
+                      // 1 tiled fp32 VALU, 2 wave per row, 3 tiled, matrix cores (chunk split),
+                      // 4 tiled, matrix cores on LDS-staged panels (16x16x32 steps)
   int far_split = 1;  // streamed SpMV: gather far-column CSR entries in a separate pass
   // SpMM variant the autotuner chose for each number of right-hand sides it was run with;
   // an explicit sable_plan_set_variant for SpMM clears it
@@ -78,6 +81,16 @@ struct FarSplit {
   DBuf<int32_t> chunk;  // [8][per_xcd] (begin, end) entry ranges, begin < 0 = none
 };
 
+// Matrix-core SpMM panels (16x16x32 bf16 steps) of the 64-row SpMM schedule: for every tile,
+// the distinct block columns its blocks touch, ascending, padded with -1 to a multiple of 32
+// (32 list positions = one panel = one k step); for every entry of the tile -> block list
+// (ordered by first column), the list position of the block's first column.
+struct MmPanels {
+  DBuf<int32_t> kcol;  // tile t: kcol[kptr[t] .. kptr[t + 1])
+  DBuf<int32_t> kptr;  // ntiles + 1 offsets, multiples of 32
+  DBuf<int32_t> bpos;  // aligned with the schedule's tile_blk
+};
+
 struct Schedule {
   int rows_per_tile = 0;
   int ntiles = 0;
@@ -93,6 +106,10 @@ struct Schedule {
   // long rows is spread over several workgroups and a small input still gives about 2048
   // tiles. Empty: tile t is rows [t rows_per_tile, (t+1) rows_per_tile).
   DBuf<int32_t> row0;
+  // Row-length bins of the CSR part (binned SpMV variants; tiles of at most 256 rows): the
+  // rows of each tile grouped by bin, stable (bin_rows, absolute row ids, tile after tile),
+  // and per tile the kNumBins + 1 bin boundaries in bin_rows (empty for other schedules).
+  DBuf<int32_t> bin_rows, bin_off;
 };
 
 }  // namespace sable
@@ -134,11 +151,13 @@ struct sable_plan_s {
   sable::Schedule sched[3];        // tiles of 256, 512, 1024 rows with the formats
   sable::Schedule sched_plain[3];  // the same tilings for the whole input as CSR
   sable::Schedule sched_mm;        // 64-row tiles of the fused SpMM
+  sable::MmPanels mm_panels;       // matrix-core panels of sched_mm (with the bf16 copies)
   sable::Schedule sched_w[4];      // tiles of 256 / W rows, W = 2, 4, 8, 16 lanes per CSR row
   sable::FarSplit far;             // far-column split of the CSR part (streamed SpMV)
   sable::ExecParams prm;
   uint32_t flags = 0;
   double plan_ms = 0.0;
+  uint64_t structure_hash = 0;  // pattern of A, extractor list, thresholds (autotuning cache key)
   // run-time specialized SpMV (hipRTC module and kernel; null until sable_plan_specialize)
   void* spec_module = nullptr;
   void* spec_func = nullptr;
@@ -168,6 +187,8 @@ bool validate_csr_device(const sable_csr& A, hipStream_t s);
 void build_schedule(sable_plan_s& P, Schedule& S, int rows_per_tile, bool with_formats,
                     hipStream_t s, bool col_order = false, bool balance = false);
 void build_bf16_split(sable_plan_s& P, hipStream_t s);
+void build_mm_panels(sable_plan_s& P, hipStream_t s);
+void build_bins(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s);
 void build_far_split(sable_plan_s& P, hipStream_t s);
 void refresh_far_values(sable_plan_s& P, hipStream_t s);
 // fp64 copies of the far entries' values (from csr_val64), allocated on first use.

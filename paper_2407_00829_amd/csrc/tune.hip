@@ -2,6 +2,9 @@
 // and keeps the fastest (lanes per CSR row for SpMV; the plain baseline gets the same
 // treatment so comparisons are against a tuned CSR kernel).
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "plan.h"
@@ -9,6 +12,17 @@
 namespace sable {
 
 namespace {
+
+// Autotuning cache, process-wide: (structure hash, specialized kernel present, op, n,
+// device) -> the chosen variants. A plan whose structure has been tuned before (the same
+// matrix pattern, extractor list and thresholds, whatever the values) takes the stored choice
+// without timing anything.
+struct TuneChoice {
+  int spmv_variant, far_split, plain_variant, spmm_mode;
+};
+typedef std::tuple<uint64_t, int, int, int, int> TuneKey;
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneChoice> g_tune_cache;
 
 template <class F>
 float time_ms(F&& f, hipStream_t s, int reps) {
@@ -43,6 +57,28 @@ int pick(const std::vector<float>& t) {
 
 void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStream_t s) {
   const int reps = 10;
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  const TuneKey key{P.structure_hash, P.spec_func != nullptr, op, op == 0 ? 1 : n, dev};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      if (op == 0) {
+        P.prm.spmv_variant = it->second.spmv_variant;
+        P.prm.far_split = it->second.far_split;
+        P.prm.plain_variant = it->second.plain_variant;
+      } else {
+        auto& tuned = P.prm.spmm_tuned;
+        tuned.erase(std::remove_if(tuned.begin(), tuned.end(),
+                                   [&](const std::pair<int, int>& e) { return e.first == n; }),
+                    tuned.end());
+        P.prm.spmm_mode = it->second.spmm_mode;
+        tuned.push_back({n, P.prm.spmm_mode});
+      }
+      return;
+    }
+  }
   if (op == 0) {
     // hybrid SpMV: every variant without the far-column split, then every streamed variant
     // with it; candidates are ranked in that order, so the split is kept only where it is
@@ -50,7 +86,7 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
     std::vector<float> t;
     std::vector<std::pair<int, int>> cand;  // (variant, far split)
     P.prm.far_split = 0;
-    for (int v = 0; v <= 10; ++v) {
+    for (int v : {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 13, 14}) {
       P.prm.spmv_variant = v;
       t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
       cand.push_back({v, 0});
@@ -71,20 +107,20 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
     const int c = pick(t);
     P.prm.spmv_variant = cand[c].first;
     P.prm.far_split = cand[c].second;
-    std::vector<float> tp(13);
-    for (int v = 0; v <= 12; ++v) {
+    std::vector<float> tp(16);
+    for (int v = 0; v <= 15; ++v) {
       P.prm.plain_variant = v;
       tp[v] = time_ms([&] { launch_spmv_plain(P, x, y, s); }, s, reps);
     }
     P.prm.plain_variant = pick(tp);
   } else {
     // x / y hold X (ncols x n) and Y (nrows x n); the choice is kept per n
-    std::vector<float> t(4);
+    std::vector<float> t(5);
     auto& tuned = P.prm.spmm_tuned;
     tuned.erase(std::remove_if(tuned.begin(), tuned.end(),
                                [&](const std::pair<int, int>& e) { return e.first == n; }),
                 tuned.end());
-    for (int m = 0; m <= 3; ++m) {
+    for (int m = 0; m <= 4; ++m) {
       P.prm.spmm_mode = m;
       t[m] = time_ms([&] { launch_spmm(P, x, y, n, s); }, s, 2);
     }
@@ -92,6 +128,14 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
     tuned.push_back({n, P.prm.spmm_mode});
   }
   HIPC(hipStreamSynchronize(s));
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = TuneChoice{P.prm.spmv_variant, P.prm.far_split, P.prm.plain_variant,
+                                 P.prm.spmm_mode};
+}
+
+void autotune_cache_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache.clear();
 }
 
 }  // namespace sable
@@ -114,13 +158,19 @@ extern "C" sable_status sable_autotune(sable_plan_t p, int32_t op, int32_t n, co
   }
 }
 
+extern "C" sable_status sable_autotune_cache_clear(void) {
+  sable::clear_error();
+  sable::autotune_cache_clear();
+  return SABLE_OK;
+}
+
 extern "C" sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32_t variant) {
   sable::clear_error();
   if (!p) {
     sable::set_error("NULL plan");
     return SABLE_ERR_INVALID_ARG;
   }
-  const int maxv = op == 0 ? 11 : op == 1 ? 3 : op == 2 ? 12 : op == 3 ? 1 : -1;
+  const int maxv = op == 0 ? 14 : op == 1 ? 4 : op == 2 ? 15 : op == 3 ? 1 : -1;
   if (variant < 0 || variant > maxv) {
     sable::set_error("variant %d out of range for op %d", variant, op);
     return SABLE_ERR_INVALID_ARG;

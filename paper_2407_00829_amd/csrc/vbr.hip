@@ -151,6 +151,168 @@ __global__ __launch_bounds__(kFBThreads) void k_findblock(
   if (threadIdx.x == 0) blockbest[(i64)blockIdx.y * gridDim.x + blockIdx.x] = sh[0];
 }
 
+// ---- the sparse window scan --------------------------------------------------------------
+// The same search over the non-empty inner lines only. Lines are the residual's rows (column
+// pass) or columns (row pass, from a transpose): lidx[lptr[l] .. lptr[l + 1]) are the outer
+// indices of line l, ascending. A workgroup serves one o0 and 256 consecutive o1: it first
+// lists, in inner order, every line of the region with an entry at an outer index in
+// [o0, largest o1 of the workgroup] (its first such index `first`, and the range of its
+// entries inside the region's outer range); each lane then runs the window rule over the
+// lines with first <= its o1, counting a line's entries in [o0, o1] by binary search. Runs of
+// empty inner indices are crossed in one step: with `win` entries in the window, the scan
+// keeps dropping left columns iff the width exceeds T(win) = max(ceil(A_min / s) - 1,
+// floor(1000 win / (p s))), so an empty run either grows the window up to T(win) or slides it,
+// and within a stretch of constant `win` only the first candidate can be a strict
+// improvement (the score falls as the area grows). Results equal the dense scan's.
+struct SpanLine {
+  int32_t pos, lo, end, first;  // inner index; entries [lo, end) from outer o0 on; first outer
+};
+
+__device__ inline int line_count_le(const int32_t* __restrict__ lidx, int lo, int end, int lim) {
+  int a = lo, b = end;  // entries in [lo, end) with outer index <= lim
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (lidx[m] <= lim) a = m + 1; else b = m;
+  }
+  return a - lo;
+}
+
+__global__ __launch_bounds__(kFBThreads) void k_findblock_sparse(
+    const int32_t* __restrict__ lptr, const int32_t* __restrict__ lidx, int in0, int out0, int Lout,
+    int Lin, i64 amin, int p, int smin, int o0_base, SpanLine* __restrict__ scratch,
+    Cand* __restrict__ blockbest) {
+  __shared__ int wsum[kFBThreads / 64];
+  __shared__ Cand sh[kFBThreads];
+  const int o0 = o0_base + blockIdx.y;
+  const int o1_first = o0 + smin - 1 + blockIdx.x * kFBThreads;
+  const int o1 = o1_first + threadIdx.x;
+  const int o1max = min(Lout - 1, o1_first + kFBThreads - 1);
+  SpanLine* list = scratch + ((i64)blockIdx.y * gridDim.x + blockIdx.x) * Lin;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int m = 0;
+  if (o1_first < Lout) {  // the same for the whole workgroup
+    for (int ib = 0; ib < Lin; ib += kFBThreads) {
+      const int i = ib + threadIdx.x;
+      SpanLine L;
+      bool keep = false;
+      if (i < Lin) {
+        const int a = lptr[in0 + i], b = lptr[in0 + i + 1];
+        int lo = a, hi = b;  // first entry at outer >= out0 + o0
+        while (lo < hi) { const int mm = (lo + hi) >> 1; if (lidx[mm] < out0 + o0) lo = mm + 1; else hi = mm; }
+        if (lo < b && lidx[lo] - out0 <= o1max) {
+          int e0 = lo, e1 = b;  // end of the entries inside the region's outer range
+          while (e0 < e1) { const int mm = (e0 + e1) >> 1; if (lidx[mm] < out0 + Lout) e0 = mm + 1; else e1 = mm; }
+          L.pos = i; L.lo = lo; L.end = e0; L.first = lidx[lo] - out0;
+          keep = true;
+        }
+      }
+      const uint64_t bal = __ballot(keep);
+      if (lane == 0) wsum[wv] = __popcll(bal);
+      __syncthreads();
+      int before = m;
+      for (int w = 0; w < wv; ++w) before += wsum[w];
+      if (keep) list[before + __popcll(bal & ((1ull << lane) - 1ull))] = L;
+      for (int w = 0; w < kFBThreads / 64; ++w) m += wsum[w];
+      __syncthreads();
+    }
+  }
+  Cand best;
+  best.nnz = -1; best.area = 0; best.o0 = o0; best.o1 = o1; best.i0 = 0; best.i1 = 0;
+  if (o1 < Lout) {
+    const i64 s = o1 - o0 + 1;
+    const i64 A = amin > 0 ? (amin + s - 1) / s : 0;  // smallest width that is large enough
+    const i64 wmin = A > 1 ? A : 1;
+    const i64 pd = (i64)p * s;
+    auto T = [&](i64 win) -> i64 {
+      const i64 D = p > 0 ? (1000 * win) / pd : ((i64)1 << 60);
+      return D > A - 1 ? D : A - 1;
+    };
+    auto valid = [&](int k) {  // next listed line visible to this lane, from k on
+      while (k < m && list[k].first > o1) ++k;
+      return k;
+    };
+    auto posk = [&](int k) -> i64 { return k < m ? list[k].pos : Lin; };
+    auto cntk = [&](int k) -> i64 { return line_count_le(lidx, list[k].lo, list[k].end, out0 + o1); };
+    int kr = valid(0), kl = kr;
+    i64 i0 = 0, i1 = -1, win = 0;
+    bool tested = false;
+    auto shrink = [&]() {
+      for (;;) {
+        const i64 w = i1 - i0 + 1, t = T(win);
+        if (w <= t) return;
+        const i64 z = posk(kl) - i0;
+        if (z > 0) { i0 += z < w - t ? z : w - t; continue; }
+        win -= cntk(kl);
+        kl = valid(kl + 1);
+        ++i0;
+        tested = false;
+      }
+    };
+    auto test = [&]() {
+      const i64 w = i1 - i0 + 1;
+      if (tested || w < wmin) return;
+      tested = true;
+      const i64 a = s * w;
+      if (score_gt(win, a, best.nnz, best.area)) {
+        best.nnz = win; best.area = a; best.i0 = (int32_t)i0; best.i1 = (int32_t)i1;
+      }
+    };
+    for (;;) {
+      i64 rem = posk(kr) - (i1 + 1);  // empty inner indices before the next listed line
+      while (rem > 0) {
+        const i64 w = i1 - i0 + 1, t = T(win);
+        if (w < t) {  // the window grows, nothing leaves
+          const i64 k = rem < t - w ? rem : t - w;
+          const i64 wc = w + 1 > wmin ? w + 1 : wmin;
+          if (!tested && wc <= w + k) { i1 += wc - w; test(); i1 += w + k - wc; }
+          else i1 += k;
+          rem -= k;
+          continue;
+        }
+        const i64 z = posk(kl) - i0;  // w == t: each step drops a column at the left
+        if (z > 0) {
+          const i64 k = rem < z ? rem : z;
+          ++i1; ++i0; test();
+          i1 += k - 1; i0 += k - 1;
+          rem -= k;
+          continue;
+        }
+        ++i1; shrink(); test(); --rem;
+      }
+      if (kr >= m) break;
+      i1 = list[kr].pos;
+      win += cntk(kr);
+      kr = valid(kr + 1);
+      tested = false;
+      shrink(); test();
+    }
+  }
+  sh[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = kFBThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w && cand_better(sh[threadIdx.x + w], sh[threadIdx.x]))
+      sh[threadIdx.x] = sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blockbest[(i64)o0 * gridDim.x + blockIdx.x] = sh[0];
+}
+
+// Transpose of the residual's pattern: rows of every column, ascending (keys column:row).
+__global__ void k_colrow_keys(const int32_t* __restrict__ rows, const int32_t* __restrict__ col,
+                              i64 nnz, uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+                              int32_t* __restrict__ ccount) {
+  for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < nnz; k += (i64)gridDim.x * blockDim.x) {
+    keys[k] = ((uint64_t)(uint32_t)col[k] << 32) | (uint32_t)rows[k];
+    vals[k] = 0;
+    atomicAdd(&ccount[col[k]], 1);
+  }
+}
+
+__global__ void k_key_low(const uint64_t* __restrict__ keys, i64 n, int32_t* __restrict__ out) {
+  for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x)
+    out[k] = (int32_t)(uint32_t)(keys[k] & 0xffffffffu);
+}
+
 __global__ __launch_bounds__(1024) void k_reduce_cand(const Cand* __restrict__ in, i64 n,
                                                       Cand* __restrict__ out) {
   __shared__ Cand sh[1024];
@@ -350,11 +512,16 @@ i64 ceil_sqrt(i64 a) {
   return s;
 }
 
+bool paper_fits(i64 nrows, i64 ncols);
+
 struct PaperCtx {
   const Resid* R;
   const sable_thresholds* th;
   hipStream_t s;
-  DBuf<int32_t> PT, QT;
+  bool sparse = false;           // window scans over non-empty inner lines (equal results)
+  DBuf<int32_t> PT, QT;          // dense scan: prefix tables
+  DBuf<int32_t> cptr, crow;      // sparse scan: the residual's columns (rows ascending)
+  DBuf<SpanLine> lines;          // sparse scan: per-workgroup line lists
   DBuf<Cand> blockbest, best1;
   std::vector<char> used_r, used_c;
   std::vector<TrimOut> out;
@@ -372,6 +539,29 @@ Cand find_block(PaperCtx& C, const BlkRec& reg, bool by_rows) {
   dim3 grid(nblocks(n_o1, kFBThreads), Lout);
   const i64 nbest = (i64)grid.x * grid.y;
   if ((i64)C.blockbest.n < nbest) C.blockbest.alloc(nbest);
+  if (C.sparse) {
+    // inner lines: columns (row pass, from the transpose) or rows (column pass)
+    const int32_t* lptr = by_rows ? C.cptr.p : R.ptr.p;
+    const int32_t* lidx = by_rows ? C.crow.p : R.col.p;
+    const int in0 = by_rows ? reg.c0 : reg.r0;
+    const int out0 = by_rows ? reg.r0 : reg.c0;
+    // o0 in batches whose line lists fit 256 MB of scratch
+    const i64 per_o0 = (i64)grid.x * Lin;
+    const int batch = (int)std::max<i64>(1, std::min<i64>(Lout, ((i64)1 << 24) / std::max<i64>(1, per_o0)));
+    if ((i64)C.lines.n < per_o0 * batch) C.lines.alloc(per_o0 * batch);
+    for (int ob = 0; ob < Lout; ob += batch) {
+      dim3 g2(grid.x, std::min(batch, Lout - ob));
+      k_findblock_sparse<<<g2, kFBThreads, 0, C.s>>>(lptr, lidx, in0, out0, Lout, Lin,
+                                                     C.th->amin_block, C.th->delta_block_pm, smin,
+                                                     ob, C.lines.p, C.blockbest.p);
+      LAUNCH_CHECK();
+    }
+    k_reduce_cand<<<1, 1024, 0, C.s>>>(C.blockbest.p, nbest, C.best1.p);
+    LAUNCH_CHECK();
+    std::vector<Cand> h;
+    to_host(h, C.best1.p, 1, C.s);
+    return h[0];
+  }
   const int32_t* T = by_rows ? C.PT.p : C.QT.p;
   const i64 S = by_rows ? R.nrows + 1 : R.ncols + 1;
   const int in0 = by_rows ? reg.c0 : reg.r0;
@@ -404,8 +594,15 @@ void decompose(PaperCtx& C, BlkRec reg) {
   for (int r = B.r0; r < B.r1; ++r) if (C.used_r[r]) return;
   for (int c = B.c0; c < B.c1; ++c) if (C.used_c[c]) return;
   DBuf<TrimOut> d(1);
-  k_trim_tables<<<1, 1, 0, C.s>>>(C.PT.p, C.QT.p, C.R->nrows, C.R->ncols, B.r0, B.r1, B.c0,
-                                  B.c1, d.p);
+  if (C.sparse) {  // counts from the residual's rows
+    DBuf<BlkRec> rb(1);
+    std::vector<BlkRec> hb{B};
+    to_dev(rb, hb, C.s);
+    k_trim_rects<<<1, 64, 0, C.s>>>(C.R->ptr.p, C.R->col.p, rb.p, 1, d.p);
+  } else {
+    k_trim_tables<<<1, 1, 0, C.s>>>(C.PT.p, C.QT.p, C.R->nrows, C.R->ncols, B.r0, B.r1, B.c0,
+                                    B.c1, d.p);
+  }
   LAUNCH_CHECK();
   std::vector<TrimOut> t;
   to_host(t, d.p, 1, C.s);
@@ -427,7 +624,27 @@ std::vector<TrimOut> blocks_paper(const Resid& R, const sable_thresholds& th, hi
   C.th = &th;
   C.s = s;
   C.best1.alloc(1);
-  {
+  C.sparse = (th.flags & SABLE_F_SPARSE_SEARCH) || !paper_fits(R.nrows, R.ncols);
+  if (C.sparse) {
+    DBuf<int32_t> rows;
+    entry_rows(R, rows, s);
+    DBuf<uint64_t> keys(R.nnz);
+    DBuf<int32_t> vals(R.nnz), cnt(R.ncols);
+    if (R.ncols) HIPC(hipMemsetAsync(cnt.p, 0, R.ncols * sizeof(int32_t), s));
+    if (R.nnz) {
+      k_colrow_keys<<<grid_for(R.nnz, 256), 256, 0, s>>>(rows.p, R.col.p, R.nnz, keys.p, vals.p, cnt.p);
+      LAUNCH_CHECK();
+      sort_pairs_u64(keys, vals, R.nnz, 64, s);
+    }
+    C.crow.alloc(R.nnz);
+    if (R.nnz) {
+      k_key_low<<<grid_for(R.nnz, 256), 256, 0, s>>>(keys.p, R.nnz, C.crow.p);
+      LAUNCH_CHECK();
+    }
+    C.cptr.alloc((i64)R.ncols + 1);
+    exclusive_scan_i32(cnt.p, C.cptr.p, R.ncols, s);
+    HIPC(hipStreamSynchronize(s));
+  } else {
     DBuf<uint8_t> occ((i64)R.nrows * R.ncols);
     if (occ.n) HIPC(hipMemsetAsync(occ.p, 0, occ.n, s));
     if (R.nnz)
@@ -572,9 +789,62 @@ bool paper_fits(i64 nrows, i64 ncols) {
   return (unsigned __int128)nrows * (unsigned __int128)ncols * m <= ((unsigned __int128)1 << 37);
 }
 
+typedef unsigned __int128 u128;
+constexpr u128 kSearchBudget = (u128)1 << 37;
+
+// Spans (o0, o1) of one pass with o1 - o0 + 1 >= smin over n outer slices.
+u128 span_pairs(i64 n, i64 smin) {
+  const u128 k = n >= smin ? (u128)(n - smin + 1) : 0;
+  return k * (k + 1) / 2;
+}
+
+// Work of the sparse scan over one pass: over the spans (o0, o1), o1 - o0 + 1 >= smin, one step
+// plus min(Lin, entries of the span). The entries grow with o1, so for each o0 a binary search
+// over the prefix sums P finds where they reach Lin, and the sum below that point comes from
+// the prefix sums of P.
+u128 scan_cost(const std::vector<i64>& cnt, i64 Lin, i64 smin) {
+  const i64 n = (i64)cnt.size();
+  std::vector<i64> P(n + 1, 0), Q(n + 2, 0);
+  for (i64 i = 0; i < n; ++i) P[i + 1] = P[i] + cnt[i];
+  for (i64 i = 0; i <= n; ++i) Q[i + 1] = Q[i] + P[i];
+  u128 total = 0;
+  for (i64 o0 = 0; o0 < n; ++o0) {
+    const i64 a = o0 + smin - 1;
+    if (a >= n) break;
+    const i64 t = (i64)(std::lower_bound(P.begin() + a + 1, P.end(), P[o0] + Lin) - P.begin()) - 1;
+    total += (u128)(n - a);
+    total += (u128)((Q[t + 1] - Q[a + 1]) - (t - a) * P[o0]);
+    total += (u128)(n - t) * (u128)Lin;
+  }
+  return total;
+}
+
+// Budget of the literal search on the VBR extractor's input: the dense scan's bound
+// nrows * ncols * max(nrows, ncols) <= 2^37, or the sparse scan's work on this residual
+// (rows pass + columns pass) <= 2^37.
+bool paper_allowed(const Resid& R, const sable_thresholds& th, hipStream_t s) {
+  if (paper_fits(R.nrows, R.ncols)) return true;
+  const i64 smin = ceil_sqrt(th.amin_block);
+  if (span_pairs(R.nrows, smin) + span_pairs(R.ncols, smin) > kSearchBudget) return false;
+  std::vector<int32_t> ptr, col;
+  to_host(ptr, R.ptr.p, (size_t)R.nrows + 1, s);
+  to_host(col, R.col.p, (size_t)R.nnz, s);
+  std::vector<i64> rc(R.nrows), cc(R.ncols, 0);
+  for (int i = 0; i < R.nrows; ++i) rc[i] = ptr[i + 1] - ptr[i];
+  for (int32_t c : col) cc[c] += 1;
+  const u128 rows = scan_cost(rc, R.ncols, smin);
+  return rows <= kSearchBudget && rows + scan_cost(cc, R.nrows, smin) <= kSearchBudget;
+}
+
 }  // namespace
 
-bool vbr_paper_fits(i64 nrows, i64 ncols) { return paper_fits(nrows, ncols); }
+// Before any GPU work: false only when even one step per span exceeds the budget (then no
+// residual of these dimensions can be searched literally).
+bool vbr_paper_fits(i64 nrows, i64 ncols, i64 amin) {
+  if (paper_fits(nrows, ncols)) return true;
+  const i64 smin = ceil_sqrt(amin);
+  return span_pairs(nrows, smin) + span_pairs(ncols, smin) <= kSearchBudget;
+}
 
 void blocks_none(sable_plan_s& P, const sable_thresholds& th, int mode) {
   if (mode == SABLE_VBR_AUTO) mode = paper_fits(P.nrows, P.ncols) ? SABLE_VBR_PAPER : SABLE_VBR_TILED;
@@ -584,7 +854,10 @@ void blocks_none(sable_plan_s& P, const sable_thresholds& th, int mode) {
 
 void extract_blocks(sable_plan_s& P, const Resid& R, const sable_thresholds& th, int mode,
                     DBuf<uint8_t>& claimed, hipStream_t s) {
-  if (mode == SABLE_VBR_AUTO) mode = paper_fits(R.nrows, R.ncols) ? SABLE_VBR_PAPER : SABLE_VBR_TILED;
+  if (mode == SABLE_VBR_AUTO) mode = paper_allowed(R, th, s) ? SABLE_VBR_PAPER : SABLE_VBR_TILED;
+  else if (mode == SABLE_VBR_PAPER && !paper_allowed(R, th, s))
+    SB_THROW(SABLE_ERR_TOO_LARGE, "literal block search over budget for this %dx%d residual",
+             R.nrows, R.ncols);
   std::vector<TrimOut> B;
   int T = 0;
   if (mode == SABLE_VBR_PAPER) B = blocks_paper(R, th, s);

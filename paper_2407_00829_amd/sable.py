@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsable.so")
 SABLE_X_VDIA, SABLE_X_VBR, SABLE_X_CSR = 1, 2, 3
 SABLE_VBR_AUTO, SABLE_VBR_PAPER, SABLE_VBR_TILED = 0, 1, 2
 SABLE_F_SPLIT_BF16 = 1
+SABLE_F_SPARSE_SEARCH = 2
 SABLE_NFEAT = 140
 SABLE_NCLASS = 15
 SABLE_MLP_NPARAM = 128 * 140 + 128 + 128 * 128 + 128 + 15 * 128 + 15
@@ -32,7 +33,7 @@ EXPORTED = [
     "sable_mlp_forward", "sable_mlp_train_step", "sable_plan_exhaustive", "sable_plan_auto", "sable_batch_create", "sable_batch_run",
     "sable_batch_latencies", "sable_batch_destroy", "sable_last_error",
     "sable_update_values_f64", "sable_spmv_f64", "sable_spmm_f64", "sable_plan_specialize",
-    "sable_error_norm_f64_noalloc",
+    "sable_error_norm_f64_noalloc", "sable_autotune_cache_clear",
 ]
 
 
@@ -71,14 +72,15 @@ class sable_plan_stats(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("plan_ms", ctypes.c_double),
                 ("spmv_variant", ctypes.c_int32), ("spmm_variant", ctypes.c_int32),
                 ("plain_variant", ctypes.c_int32), ("far_split", ctypes.c_int32),
-                ("far_nnz", ctypes.c_int64), ("spec_ms", ctypes.c_double)]
+                ("far_nnz", ctypes.c_int64), ("spec_ms", ctypes.c_double),
+                ("structure_hash", ctypes.c_uint64)]
 
 
 class sable_partition_host(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in (
         "vdia_val", "idiag", "seg_row_start", "seg_nrows", "seg_ndiags", "seg_val_ptr",
         "seg_idiag_ptr", "blk", "blk_val_ptr", "vbr_val", "csr_ptr", "csr_col", "csr_val",
-        "owner", "slot")]
+        "owner", "slot", "vbr_bf16")]
 
 
 class sable_batch_item(ctypes.Structure):
@@ -111,6 +113,7 @@ def lib():
         "sable_error_norm_f64_noalloc": [P, P, i64, P, P],
         "sable_update_values": [P, P, P],
         "sable_autotune": [P, i32, i32, P, P, P],
+        "sable_autotune_cache_clear": [],
         "sable_plan_set_variant": [P, i32, i32],
         "sable_features": [P, P, P],
         "sable_class_plan": [i32, P, P, P],
@@ -243,7 +246,7 @@ def sable_plan_export(p: Plan) -> dict:
         blk_val_ptr=np.zeros(nblk, np.int64), vbr_val=np.zeros(st["vbr_cells"], np.float32),
         csr_ptr=np.zeros(st["nrows"] + 1, np.int64), csr_col=np.zeros(st["csr_nnz"], np.int32),
         csr_val=np.zeros(st["csr_nnz"], np.float32), owner=np.zeros(st["nnz"], np.int8),
-        slot=np.zeros(st["nnz"], np.int64))
+        slot=np.zeros(st["nnz"], np.int64), vbr_bf16=np.zeros(st["vbr_cells"], np.uint32))
     ph = sable_partition_host(*[out[k].ctypes.data_as(ctypes.c_void_p) for k, _ in
                                 sable_partition_host._fields_])
     _check("sable_plan_export", lib().sable_plan_export(p.h, ctypes.byref(ph)))
@@ -321,6 +324,10 @@ def sable_error_norm_f64_noalloc(y, yref, out, stream=None) -> None:
 def sable_autotune(p: Plan, op: int, n: int, x, y, stream=None) -> None:
     _check("sable_autotune", lib().sable_autotune(p.h, int(op), int(n), _ptr(x), _ptr(y),
                                                   _stream(stream)))
+
+
+def sable_autotune_cache_clear() -> None:
+    _check("sable_autotune_cache_clear", lib().sable_autotune_cache_clear())
 
 
 def sable_plan_set_variant(p: Plan, op: int, variant: int) -> None:

@@ -52,8 +52,9 @@ def test_bad_lists_and_sizes():
     assert _plan_rc(_fake_csr(), [7, sable.SABLE_X_CSR])[0] == 1
     assert _plan_rc(_fake_csr(nnz=2 ** 31), [sable.SABLE_X_CSR])[0] == 4
     assert _plan_rc(_fake_csr(nrows=-1), [sable.SABLE_X_CSR])[0] == 1
-    # literal block search over budget (6000^3 > 2^37)
-    A = _fake_csr(6000, 6000, 5)
+    # literal block search over budget before any GPU work: 400,000^2 has about 1.6e11
+    # spans of at least ceil(sqrt(2500)) rows or columns, one step each is past 2^37
+    A = _fake_csr(400000, 400000, 5)
     assert _plan_rc(A, [sable.SABLE_X_VBR, sable.SABLE_X_CSR], sable.SABLE_VBR_PAPER)[0] == 4
     th = sable.Thresholds(delta_block_pm=400)
     assert _plan_rc(_fake_csr(), [sable.SABLE_X_VBR, sable.SABLE_X_CSR], 0, th)[0] == 1

@@ -206,6 +206,9 @@ def test_invalid_csr_rejected():
 
 
 def test_update_values_matches_replan():
+    """New values through sable_update_values give the same formats (fp32 values and the
+    split-bf16 words), the same SpMV and the same SpMM under every SpMM variant, bit for bit,
+    as planning again with those values."""
     A, x = synth.gen_c1(1, n=768)
     th = oracle.Thresholds(amin_band=256, amin_block=256)
     kinds = [V, B, C]
@@ -216,9 +219,65 @@ def test_update_values_matches_replan():
     sable.sable_update_values(p, torch.from_numpy(A2.values).cuda())
     torch.cuda.synchronize()
     q = gpu_plan(A2, kinds, oracle.MODE_PAPER, th)
-    assert_same_partition(sable.sable_plan_export(p), sable.sable_plan_export(q))
+    ep, eq = sable.sable_plan_export(p), sable.sable_plan_export(q)
+    assert_same_partition(ep, eq)
+    assert ep["vbr_bf16"].size > 0
+    assert np.array_equal(ep["vbr_bf16"], eq["vbr_bf16"])
     y1, y2 = run_spmv(p, A2, x), run_spmv(q, A2, x)
     assert torch.equal(y1, y2)
+    n = 24
+    Xd = torch.from_numpy(synth.gen_dense_matrix(5, A.ncols, n)).cuda()
+    for mode in range(5):
+        sable.sable_plan_set_variant(p, 1, mode)
+        sable.sable_plan_set_variant(q, 1, mode)
+        Y1 = torch.full((A.nrows, n), float("nan"), device="cuda")
+        Y2 = torch.full((A.nrows, n), float("nan"), device="cuda")
+        sable.sable_spmm(p, Xd, Y1, n)
+        sable.sable_spmm(q, Xd, Y2, n)
+        torch.cuda.synchronize()
+        assert torch.equal(Y1, Y2), mode
+
+
+def bf16_words(vals):
+    hi, lo = oracle.bf16_split(vals)
+    return hi.astype(np.uint32) | (lo.astype(np.uint32) << 16)
+
+
+@pytest.mark.parametrize("case", ["c1_tiled", "fem", "odd_shapes"])
+def test_bf16_split_words_bit_exact(case):
+    """The plan's split-bf16 copy of every block cell (the words the matrix-core SpMM
+    multiplies) equals the oracle's round-to-nearest-even split of the fp32 value bit for
+    bit, fill cells included (zero words)."""
+    if case == "c1_tiled":
+        A, _ = synth.gen_c1(5, n=2048)
+        th = oracle.Thresholds(amin_band=256, amin_block=256)
+        p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
+    elif case == "fem":
+        A, _ = synth.gen_c3(2, n=6000, ystride=8, zstride=64, scatter_density=2e-4,
+                            with_x=False)
+        th = oracle.Thresholds(delta_band_pm=900, delta_block_pm=900, amin_block=36)
+        p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
+    else:  # blocks of widths not a multiple of 4, values with long mantissas and signs
+        rng = np.random.default_rng(11)
+        rows, cols = [], []
+        for (r0, h, c0, w) in [(0, 7, 3, 9), (20, 13, 40, 5), (50, 3, 0, 31), (70, 17, 60, 2)]:
+            rr, cc = np.meshgrid(np.arange(r0, r0 + h), np.arange(c0, c0 + w), indexing="ij")
+            keep = rng.random(rr.size) < 0.8
+            rows.append(rr.ravel()[keep])
+            cols.append(cc.ravel()[keep])
+        r, c = np.concatenate(rows), np.concatenate(cols)
+        v = (rng.standard_normal(r.size) * 10.0 ** rng.integers(-30, 30, r.size)).astype(np.float32)
+        A = synth.from_coo(100, 100, r, c, v)
+        p = gpu_plan(A, [B, C], oracle.MODE_TILED, oracle.Thresholds(delta_block_pm=500, amin_block=4))
+    got = sable.sable_plan_export(p)
+    assert got["vbr_val"].size > 0
+    want = bf16_words(got["vbr_val"])
+    assert np.array_equal(got["vbr_bf16"], want)
+    # the words really split: hi + lo reproduces the value to 2^-16 relative
+    hi = oracle.bf16_to_f32((got["vbr_bf16"] & 0xFFFF).astype(np.uint16)).astype(np.float64)
+    lo = oracle.bf16_to_f32((got["vbr_bf16"] >> 16).astype(np.uint16)).astype(np.float64)
+    a = got["vbr_val"].astype(np.float64)
+    assert np.all(np.abs(hi + lo - a) <= 2.0 ** -16 * np.abs(a))
 
 
 def test_plain_csr_baseline():
@@ -239,12 +298,12 @@ def test_every_spmv_variant_and_baseline():
     p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
     ref = oracle.spmv(A, x)
     xd = torch.from_numpy(x).cuda()
-    for v in range(11):
+    for v in [*range(11), 12, 13, 14]:
         sable.sable_plan_set_variant(p, 0, v)
         err = check_spmv(p, A, x)
         print(f"  variant {v}: {err:.2e}")
     y = torch.empty(A.nrows, device="cuda")
-    for v in range(13):
+    for v in range(16):
         sable.sable_plan_set_variant(p, 2, v)
         sable.sable_csr_spmv(p, xd, y)
         torch.cuda.synchronize()
@@ -263,16 +322,16 @@ def test_every_variant_on_tiny_and_ragged_shapes(shape):
     p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
     xd = torch.from_numpy(x).cuda()
     y = torch.empty(nr, device="cuda")
-    for v in range(11):
+    for v in [*range(11), 12, 13, 14]:
         sable.sable_plan_set_variant(p, 0, v)
         check_spmv(p, A, x)
-    for v in range(13):
+    for v in range(16):
         sable.sable_plan_set_variant(p, 2, v)
         sable.sable_csr_spmv(p, xd, y)
         torch.cuda.synchronize()
         assert oracle.rel_err(y.cpu().numpy(), ref) <= 1e-5, v
     X = synth.gen_dense_matrix(3, nc, 5)
-    for m in range(4):
+    for m in range(5):
         sable.sable_plan_set_variant(p, 1, m)
         Y = torch.full((nr, 5), float("nan"), device="cuda")
         sable.sable_spmm(p, torch.from_numpy(X).cuda(), Y, 5)
@@ -285,7 +344,7 @@ def test_spmm_modes_and_widths(n):
     A, _ = synth.gen_c1(4, n=1536)
     th = oracle.Thresholds(amin_band=256, amin_block=256)
     p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
-    for mode in range(4):
+    for mode in range(5):
         sable.sable_plan_set_variant(p, 1, mode)
         check_spmm(p, A, n, seed=n)
 
@@ -311,7 +370,7 @@ def test_spmm_autotune_kept_per_width():
     sable.sable_spmm(q, X16, ref, 16)
     torch.cuda.synchronize()
     assert torch.equal(Y16, ref)
-    for m in range(4):  # an explicit choice reaches every width
+    for m in range(5):  # an explicit choice reaches every width
         sable.sable_plan_set_variant(p, 1, m)
         sable.sable_plan_set_variant(q, 1, m)
         sable.sable_spmm(p, X16, Y16, 16)
@@ -330,9 +389,10 @@ def test_spmm_split_bf16_block_accuracy():
     p = gpu_plan(A, [B, C], oracle.MODE_PAPER, oracle.Thresholds(amin_block=64))
     got = sable.sable_plan_export(p)
     assert got["blk"].tolist() == [[0, 300, 0, 200]]
-    sable.sable_plan_set_variant(p, 1, 0)
-    err = check_spmm(p, A, 48, tol=2e-5)
-    assert err > 1e-8  # the matrix-core path really ran in reduced precision
+    for mode in (0, 4):
+        sable.sable_plan_set_variant(p, 1, mode)
+        err = check_spmm(p, A, 48, tol=2e-5)
+        assert err > 1e-8  # the matrix-core path really ran in reduced precision
 
 
 def test_c1_full_paper_mode_against_stored_oracle():
@@ -354,10 +414,11 @@ def test_c1_full_paper_mode_against_stored_oracle():
     check_spmv(p, A, x)
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_c2_full_size_sampled(seed):
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_c2_full_size(seed):
     """PDE-like 2,097,152-row matrix in the benchmark's configuration (autotuned kernel):
-    exact cover of every input entry, and sampled rows against the FP64 oracle."""
+    exact cover of every input entry, and the whole product vector against the FP64
+    oracle (every row), for the autotuned variant and for the plain CSR baseline."""
     A, x = synth.gen_c2(seed)
     th = oracle.Thresholds(delta_band_pm=750, delta_block_pm=500)
     p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
@@ -366,36 +427,69 @@ def test_c2_full_size_sampled(seed):
     sable.sable_autotune(p, 0, 1, xd, y)
     got = sable.sable_plan_export(p)
     oracle.check_partition(A, got, th, [V, B, C])
+    ref = oracle.spmv(A, x)
+    y.fill_(float("nan"))
     sable.sable_spmv(p, xd, y)
     torch.cuda.synchronize()
-    rows = np.random.default_rng(seed).choice(A.nrows, 20000, replace=False)
-    rows = np.concatenate([rows, [0, A.nrows - 1]])
-    err = oracle.rel_err(y.cpu().numpy()[rows], oracle.spmv_rows(A, x, rows))
-    print(f"  sampled rel_err={err:.3e}")
+    err = oracle.rel_err(y.cpu().numpy(), ref)
+    info = sable.sable_plan_info(p)
+    print(f"  full rel_err={err:.3e} (variant {info['spmv_variant']}, far split {info['far_split']})")
     assert err <= 1e-5
+    yp = torch.full((A.nrows,), float("nan"), device="cuda")
+    sable.sable_csr_spmv(p, xd, yp)
+    torch.cuda.synchronize()
+    errp = oracle.rel_err(yp.cpu().numpy(), ref)
+    print(f"  plain CSR full rel_err={errp:.3e}")
+    assert errp <= 1e-5
 
 
-def test_c3_full_size_sampled():
-    """FEM-like 500,000-row matrix, SpMM with n = 128, in the benchmark's configuration
-    (autotuned, blocks on matrix cores as split bf16): exact cover of every input entry, and
-    sampled rows (plus the first and last) against the FP64 oracle."""
+@pytest.fixture(scope="module")
+def c3_case():
+    """The FEM-like 500,000-row matrix (n = 128), its plan and the oracle's FP64 product."""
     A, X = synth.gen_c3(0)
     th = oracle.Thresholds(delta_band_pm=900, delta_block_pm=900, amin_block=36)
     p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
+    print("  oracle FP64 SpMM (n = 128)", flush=True)
+    ref = oracle.spmm(A, X)
+    return A, X, th, p, ref
+
+
+def _c3_product(p, X):
+    n = X.shape[1]
+    Xd = torch.from_numpy(X).cuda()
+    Y = torch.full((X.shape[0], n), float("nan"), device="cuda")
+    sable.sable_spmm(p, Xd, Y, n)
+    torch.cuda.synchronize()
+    return Y.cpu().numpy()
+
+
+def test_c3_full_size(c3_case):
+    """FEM-like matrix, SpMM with n = 128, in the benchmark's configuration (autotuned):
+    exact cover of every input entry, and the whole 500,000 x 128 product against the
+    FP64 oracle."""
+    A, X, th, p, ref = c3_case
     n = X.shape[1]
     Xd = torch.from_numpy(X).cuda()
     Y = torch.empty(A.nrows, n, device="cuda")
     sable.sable_autotune(p, 1, n, Xd, Y)
+    del Xd, Y
     oracle.check_partition(A, sable.sable_plan_export(p), th, [V, B, C])
-    Y.fill_(float("nan"))
-    sable.sable_spmm(p, Xd, Y, n)
-    torch.cuda.synchronize()
-    rows = np.random.default_rng(3).choice(A.nrows, 2048, replace=False)
-    rows = np.concatenate([rows, [0, A.nrows - 1]])
-    got = Y[torch.from_numpy(rows).cuda()].cpu().numpy()
-    err = oracle.rel_err(got, oracle.spmm_rows(A, X, rows))
-    print(f"  sampled rel_err={err:.3e} (spmm mode {sable.sable_plan_info(p)['spmm_variant']})")
+    err = oracle.rel_err(_c3_product(p, X), ref)
+    print(f"  full rel_err={err:.3e} (spmm variant {sable.sable_plan_info(p)['spmm_variant']})")
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("mode", [0, 3, 4])
+def test_c3_full_size_matrix_cores(c3_case, mode):
+    """The same product with the VBR blocks forced onto the split-bf16 matrix-core paths
+    (SpMM variants 0, 3 and 4): the whole product within 1e-4 of the FP64 oracle, and above
+    plain fp32 rounding (the reduced-precision path really ran)."""
+    A, X, th, p, ref = c3_case
+    sable.sable_plan_set_variant(p, 1, mode)
+    err = oracle.rel_err(_c3_product(p, X), ref)
+    print(f"  full rel_err={err:.3e} (spmm variant {mode})")
+    assert err <= 1e-4
+    assert err > 5e-7  # fp32 blocks give ~1e-7 here; split bf16 drops the lo * lo term
 
 
 # ---- far-column split of the CSR part (streamed SpMV) ------------------------------------
@@ -477,3 +571,43 @@ def test_prebound_launcher_matches_direct_calls():
     assert torch.equal(y1, y2) and torch.equal(Y1, Y2)
     with pytest.raises(sable.SableError):
         sable.launcher("sable_spmm", p, X, Y2, 0)()  # n < 1 is rejected by the entry point
+
+
+# ---- autotuning cache ----------------------------------------------------------------------
+
+def test_structure_hash_and_autotune_cache():
+    """Plans of one pattern (any values) share a structure hash and an autotuning result: the
+    second plan's sable_autotune takes the cached choice without timing; another pattern or
+    other thresholds give another hash; clearing the cache makes the next call time again."""
+    import time
+    A, x = synth.gen_c1(6, n=2048)
+    th = oracle.Thresholds(amin_band=256, amin_block=256)
+    kinds = [V, B, C]
+    A2 = synth.CSR(A.nrows, A.ncols, A.indptr, A.indices,
+                   synth.gen_dense_vector(3, A.nnz, normal=True))
+    p, q = gpu_plan(A, kinds, oracle.MODE_TILED, th), gpu_plan(A2, kinds, oracle.MODE_TILED, th)
+    hp, hq = sable.sable_plan_info(p)["structure_hash"], sable.sable_plan_info(q)["structure_hash"]
+    assert hp == hq and hp != 0
+    A3, _ = synth.gen_c1(7, n=2048)
+    assert sable.sable_plan_info(gpu_plan(A3, kinds, oracle.MODE_TILED, th))["structure_hash"] != hp
+    th2 = oracle.Thresholds(amin_band=256, amin_block=512)
+    assert sable.sable_plan_info(gpu_plan(A, kinds, oracle.MODE_TILED, th2))["structure_hash"] != hp
+    sable.sable_autotune_cache_clear()
+    xd = torch.from_numpy(x).cuda()
+    y = torch.empty(A.nrows, device="cuda")
+    t0 = time.perf_counter()
+    sable.sable_autotune(p, 0, 1, xd, y)
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sable.sable_autotune(q, 0, 1, xd, y)
+    t_cached = time.perf_counter() - t0
+    ip, iq = sable.sable_plan_info(p), sable.sable_plan_info(q)
+    for k in ("spmv_variant", "far_split", "plain_variant"):
+        assert ip[k] == iq[k], k
+    print(f"  first {t_first * 1e3:.1f} ms, cached {t_cached * 1e3:.2f} ms")
+    assert t_cached < 0.2 * t_first
+    check_spmv(q, A2, x)
+    sable.sable_autotune_cache_clear()
+    t0 = time.perf_counter()
+    sable.sable_autotune(q, 0, 1, xd, y)
+    assert time.perf_counter() - t0 > 5 * t_cached

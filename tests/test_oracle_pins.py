@@ -183,8 +183,52 @@ def test_trim_removes_sparse_edge():
     assert P["blk"].tolist() == [[20, 70, 20, 70]]
 
 
+def _search_cost_brute(A, amin):
+    """One step per outer span (o0, o1) of length >= ceil(sqrt(A_min)) of both passes, plus
+    min(inner length, entries of the span), by enumeration."""
+    D = np.zeros((A.nrows, A.ncols), np.int64)
+    D[A.rows(), A.indices.astype(np.int64)] = 1
+    smin = int(np.ceil(np.sqrt(amin) - 1e-9))
+    while smin * smin < amin:
+        smin += 1
+    total = 0
+    for M in (D, D.T):
+        cnt = M.sum(axis=1)
+        n, lin = M.shape
+        for o0 in range(n):
+            for o1 in range(o0 + smin - 1, n):
+                total += 1 + min(lin, int(cnt[o0:o1 + 1].sum()))
+    return total
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_search_cost_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    nr, nc = int(rng.integers(5, 40)), int(rng.integers(5, 40))
+    k = int(rng.integers(0, nr * nc // 3 + 1))
+    A = from_coo(nr, nc, rng.integers(0, nr, k), rng.integers(0, nc, k), np.ones(k))
+    amin = int(rng.choice([1, 4, 9, 10, 36]))
+    ok, cost = oracle.paper_fits(A, oracle.Thresholds(amin_block=amin))
+    assert ok  # small matrices always fit
+    assert cost == _search_cost_brute(A, amin)
+
+
 def test_paper_mode_budget():
+    """The literal search is allowed when nrows * ncols * max <= 2^37, or when the sparse
+    scan's work (one step per span of both passes plus min(inner length, span entries)) is
+    <= 2^37. A 6000^2 matrix with one entry is past the first bound but well within the
+    second; with eight entries per row most spans see the whole inner range, the work is
+    about 2e11 and the search is refused (auto mode takes the tiled search)."""
     A = from_coo(6000, 6000, [0], [0], [1.0])
+    ok, cost = oracle.paper_fits(A)
+    assert ok and cost < 1 << 37
+    P = oracle.plan(A, [B, C], oracle.MODE_AUTO)
+    assert P["vbr_mode"] == oracle.MODE_PAPER and P["blk"].shape[0] == 0
+    rng = np.random.default_rng(0)
+    r = np.repeat(np.arange(6000), 8)
+    A = from_coo(6000, 6000, r, rng.integers(0, 6000, r.size), np.ones(r.size))
+    ok, cost = oracle.paper_fits(A)
+    assert not ok and cost > 1 << 37
     with pytest.raises(oracle.OracleError) as e:
         oracle.plan(A, [B, C], oracle.MODE_PAPER)
     assert e.value.code == 4
