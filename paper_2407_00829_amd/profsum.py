@@ -19,7 +19,8 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("exec.h", "exec.hip", "plan.h")]
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
+                  for f in ("exec.h", "exec.hip", "plan.h", "spmm_tile.h", "spmm_panel.h")]
 
 
 def kernel_source_sha() -> str:
@@ -57,18 +58,44 @@ def timed_mean_us(trace_dir, kernel, first, count):
     return total
 
 
-def counter_mean_kib(d, kernel):
+def _dispatch_order(r):
+    for k in ("Dispatch_Id", "Correlation_Id"):
+        if k in r and r[k] not in ("", None):
+            return int(r[k])
+    return 0
+
+
+def counter_mean_kib(d, kernel, last=0):
     """Mean counter value per dispatch; kernel may name several kernels joined by ' + '
-    (one product launching each once), whose means are added."""
+    (one product launching each once), whose means are added. last > 0: only the last
+    `last` dispatches of each kernel (in dispatch order)."""
     total, count = 0.0, None
     rows = _csv(d, "counter_collection.csv")
     for k in kernel.split(" + "):
-        vals = [float(r["Counter_Value"]) for r in rows if k in r["Kernel_Name"]]
+        sel = sorted((r for r in rows if k in r["Kernel_Name"]), key=_dispatch_order)
+        vals = [float(r["Counter_Value"]) for r in sel]
+        if last:
+            vals = vals[-last:]
         if not vals:
             raise ValueError(f"kernel {k!r} not found under {d}")
         total += sum(vals) / len(vals)
         count = len(vals) if count is None else min(count, len(vals))
     return total, count
+
+
+def last_mean_us(trace_dir, kernel, count):
+    """Mean duration of the last `count` dispatches of each named kernel, summed over the
+    kernels of one product (the benchmark's final cache-cold launches)."""
+    rows = _csv(trace_dir, "kernel_trace.csv")
+    total = 0.0
+    for k in kernel.split(" + "):
+        d = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows
+                   if k in r["Kernel_Name"])
+        sel = d[-count:]
+        if len(sel) < count:
+            raise ValueError(f"only {len(d)} dispatches of {k!r}")
+        total += sum(e - b for b, e in sel) / len(sel) / 1e3
+    return total
 
 
 def pmc_summary(argv):
@@ -208,11 +235,14 @@ def main(argv=None):
                     help="add this kernel's traffic record to the existing file")
     ap.add_argument("--md-name", default="",
                     help="write the summary under this name instead of --name")
+    ap.add_argument("--last", type=int, default=0,
+                    help="counters and durations of the last N dispatches of the kernel only "
+                         "(the benchmark's final cache-cold launches)")
     a = ap.parse_args(argv)
     rows = kernel_stats(a.trace)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    f_k, nf = counter_mean_kib(a.fetch, a.kernel)
-    w_k, nw = counter_mean_kib(a.write, a.kernel)
+    f_k, nf = counter_mean_kib(a.fetch, a.kernel, a.last)
+    w_k, nw = counter_mean_kib(a.write, a.kernel, a.last)
     fc, _ = counter_mean_kib(a.fetch_copy, a.copy_kernel)
     wc, _ = counter_mean_kib(a.write_copy, a.copy_kernel)
     half = a.copy_bytes / 2  # the copy reads half and writes half of copy_bytes
@@ -234,7 +264,7 @@ def main(argv=None):
     for r in rows[:12]:
         md.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
-    md += ["", f"## HBM bytes of `{a.kernel}`", "",
+    md += ["", f"## HBM bytes of `{a.kernel}`" + (f" (last {a.last} dispatches)" if a.last else ""), "",
            f"* FETCH_SIZE mean {f_k:.1f} KiB per dispatch over {nf} dispatches; WRITE_SIZE "
            f"{w_k:.1f} KiB over {nw}.",
            f"* Calibration with a plain device copy of {a.copy_bytes / 2 ** 30:.2f} GiB "
@@ -256,6 +286,11 @@ def main(argv=None):
             md.append(f"* Timed region (dispatches {first}..{first + count - 1} of the kernel, "
                       f"after the warm-up and before the cache-cold launches): mean {tm:.2f} us -> "
                       f"{(fetch_b + write_b) / (tm * 1e-6) / 1e12:.2f} TB/s of counted traffic.")
+        if a.last:
+            tm = last_mean_us(a.trace, a.kernel, a.last)
+            md.append(f"* Last {a.last} dispatches of the kernel (the cache-cold launches): mean "
+                      f"{tm:.2f} us -> {(fetch_b + write_b) / (tm * 1e-6) / 1e12:.2f} TB/s of "
+                      "counted traffic.")
     os.makedirs(a.out, exist_ok=True)
     with open(os.path.join(a.out, f"{a.md_name or a.name}.md"), "w") as f:
         f.write("\n".join(md) + "\n")
