@@ -268,7 +268,7 @@ sable::i64 sable_plan_s::device_bytes() const {
                                                                                        : &sched_w[k - 7];
     b += S->tile_seg_lo.bytes() + S->tile_seg_hi.bytes() + S->tile_blk_ptr.bytes() +
          S->tile_blk.bytes() + S->order.bytes() + S->row0.bytes() + S->bin_rows.bytes() +
-         S->bin_off.bytes();
+         S->bin_off.bytes() + S->head.bytes();
   }
   b += mm_panels.kcol.bytes() + mm_panels.kptr.bytes() + mm_panels.bpos.bytes();
   b += far.ccol.bytes() + far.far_col.bytes() + far.far_src.bytes() + far.far_val.bytes() +

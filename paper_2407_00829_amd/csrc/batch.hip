@@ -74,8 +74,7 @@ __device__ __forceinline__ void batch_units(const PlanView* __restrict__ views,
     const PlanView& P = views[it];
     int local = (int)(u - off[lo]);
     if constexpr (OP == 0) {
-      if (P.tile_order) local = P.tile_order[local];
-      spmv_tile_stream<1>(P, local, I.x, I.y, lds);
+      spmv_tile_stream<1>(P, local, I.x, I.y, lds);  // local = launch slot
     } else {
       int rt = local % I.units_per_col;
       const int cc = local / I.units_per_col;

@@ -30,6 +30,7 @@ struct PlanView {
   const int32_t* tile_blk_ptr;
   const int32_t* tile_blk;
   const int32_t* tile_order;  // launch order of the streamed kernels (may be null)
+  const TileHead* tile_head;  // streamed kernels: per launch slot (null for other schedules)
   const int32_t* tile_row0;   // tile row bounds (entry-balanced tiling; null: uniform)
   // fp64 copies of the values (FP64 executor; null until set)
   const double* vdia_val64;
@@ -246,8 +247,9 @@ __device__ __forceinline__ void csr_finish(const CsrFlight<T, U>& f, int e0, int
   }
 }
 
+// slot: the launch slot (the tile is the slot's record's).
 template <int RPT, bool NT = false, class T = float>
-__device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
+__device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int slot,
                                                  const T* __restrict__ x,
                                                  T* __restrict__ y, float* __restrict__ lds) {
   constexpr int RT = kSpmvThreads * RPT;
@@ -255,13 +257,13 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
   constexpr int kPass = U * kSpmvThreads;
   T* prod = reinterpret_cast<T*>(lds);  // kPass products (lds holds kCsrChunk + RT values of T)
   T* part = prod + kCsrChunk;           // RT block partials
-  int r0, rend;
-  tile_rows(P, tile, r0, rend);
+  const TileHead H = P.tile_head[slot];  // uniform: one scalar load of the whole record
+  const int r0 = H.r0, rend = H.rend;
   const int t = threadIdx.x;
   // 0. independent loads, then the first CSR pass
-  const int e_begin = P.csr_ptr[r0], e_end = P.csr_ptr[rend];
-  const int slo = P.tile_seg_lo[tile], shi = P.tile_seg_hi[tile];
-  const int blo = P.tile_blk_ptr[tile], bhi = P.tile_blk_ptr[tile + 1];
+  const int e_begin = H.e0, e_end = H.e1;
+  const int slo = H.slo, shi = H.shi;
+  const int blo = H.blo, bhi = H.bhi;
   int kb[RPT], ke[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
@@ -269,16 +271,9 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int tile,
     kb[q] = r < rend ? P.csr_ptr[r] : 0;
     ke[q] = r < rend ? P.csr_ptr[r + 1] : 0;
   }
-  int rs = 0, nr = 0, nd = 0;
-  i64 svp = 0;
-  int sip = 0;
-  if (slo < shi) {
-    rs = P.seg_row_start[slo];
-    nr = P.seg_nrows[slo];
-    nd = P.seg_ndiags[slo];
-    svp = P.seg_val_ptr[slo];
-    sip = P.seg_idiag_ptr[slo];
-  }
+  int rs = H.rs, nr = H.nr, nd = H.nd;
+  i64 svp = H.svp;
+  int sip = H.sip;
   CsrFlight<T, U> fl;
   if (e_begin < e_end) csr_issue<T, NT, U>(P, e_begin, e_end, x, fl);
 

@@ -21,6 +21,7 @@ PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool fa
   v.tile_blk_ptr = S.tile_blk_ptr.p;
   v.tile_blk = S.tile_blk.p;
   v.tile_order = S.order.p;
+  v.tile_head = S.head.p;
   v.tile_row0 = S.row0.p;
   v.vdia_val64 = P.vdia_val64.p;
   v.vbr_val64 = P.vbr_val64.p;
@@ -219,10 +220,9 @@ template <int RPT, bool NT>
 __global__ __launch_bounds__(256) void k_spmv_stream(PlanView P, const float* __restrict__ x,
                                                     float* __restrict__ y) {
   __shared__ float lds[kCsrChunk + kSpmvThreads * RPT];
-  int tile = xcd_tile(blockIdx.x, P.ntiles);
-  if (tile >= P.ntiles) return;
-  if (P.tile_order) tile = P.tile_order[tile];
-  spmv_tile_stream<RPT, NT>(P, tile, x, y, lds);
+  const int slot = xcd_tile(blockIdx.x, P.ntiles);
+  if (slot >= P.ntiles) return;
+  spmv_tile_stream<RPT, NT>(P, slot, x, y, lds);
 }
 
 // Row-length bins: subwave widths per bin (u = log2 of entries per lane).
@@ -318,10 +318,9 @@ template <int RPT, bool NT>
 __global__ __launch_bounds__(256) void k_csr_stream(PlanView P, const float* __restrict__ x,
                                                    float* __restrict__ y) {
   __shared__ float lds[kCsrChunk + kSpmvThreads * RPT];
-  int tile = xcd_tile(blockIdx.x, P.ntiles);
-  if (tile >= P.ntiles) return;
-  if (P.tile_order) tile = P.tile_order[tile];
-  spmv_tile_stream<RPT, NT>(P, tile, x, y, lds);
+  const int slot = xcd_tile(blockIdx.x, P.ntiles);
+  if (slot >= P.ntiles) return;
+  spmv_tile_stream<RPT, NT>(P, slot, x, y, lds);
 }
 
 template <int W>
@@ -373,10 +372,9 @@ template <int RPT>
 __global__ __launch_bounds__(256) void k_spmv_stream_f64(PlanView P, const double* __restrict__ x,
                                                         double* __restrict__ y) {
   __shared__ double lds[kCsrChunk + kSpmvThreads * RPT];
-  int tile = xcd_tile(blockIdx.x, P.ntiles);
-  if (tile >= P.ntiles) return;
-  if (P.tile_order) tile = P.tile_order[tile];
-  spmv_tile_stream<RPT, false, double>(P, tile, x, y, reinterpret_cast<float*>(lds));
+  const int slot = xcd_tile(blockIdx.x, P.ntiles);
+  if (slot >= P.ntiles) return;
+  spmv_tile_stream<RPT, false, double>(P, slot, x, y, reinterpret_cast<float*>(lds));
 }
 
 __global__ __launch_bounds__(kMmThreads) void k_spmm_tile_f64(PlanView P, const double* __restrict__ X,
@@ -439,6 +437,8 @@ __global__ __launch_bounds__(256) void k_spmm_fused_valu(PlanView P, const float
 
 static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s);
 
+static void build_heads(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s);
+
 void build_schedule(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hipStream_t s,
                     bool col_order, bool balance) {
   S.row0.reset();
@@ -467,6 +467,55 @@ void build_schedule(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hip
   }
   build_tiles(P, S, RT, with_formats, col_order, s);
   build_order(P, S, with_formats, s);
+  if (balance) build_heads(P, S, with_formats, s);
+}
+
+// One record per launch slot of a streamed SpMV schedule (host-side from the tile tables).
+static void build_heads(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s) {
+  S.head.reset();
+  const int nt = S.ntiles;
+  if (nt == 0) return;
+  std::vector<int32_t> ptr, row0, ord, slo, shi, bptr;
+  to_host(ptr, with_formats ? P.csr_ptr.p : P.a_ptr.p, (size_t)P.nrows + 1, s);
+  if (S.row0.p) to_host(row0, S.row0.p, (size_t)nt + 1, s);
+  if (S.order.p) to_host(ord, S.order.p, (size_t)nt, s);
+  to_host(slo, S.tile_seg_lo.p, (size_t)nt, s);
+  to_host(shi, S.tile_seg_hi.p, (size_t)nt, s);
+  to_host(bptr, S.tile_blk_ptr.p, (size_t)nt + 1, s);
+  const int nseg = with_formats ? P.nseg : 0;
+  std::vector<int32_t> srs, snr, snd, sip;
+  std::vector<i64> svp;
+  if (nseg) {
+    to_host(srs, P.seg_row_start.p, nseg, s);
+    to_host(snr, P.seg_nrows.p, nseg, s);
+    to_host(snd, P.seg_ndiags.p, nseg, s);
+    to_host(sip, P.seg_idiag_ptr.p, nseg, s);
+    to_host(svp, P.seg_val_ptr.p, nseg, s);
+  }
+  std::vector<TileHead> h(nt);
+  for (int k = 0; k < nt; ++k) {
+    const int t = S.order.p ? ord[k] : k;
+    TileHead& H = h[k];
+    std::memset(&H, 0, sizeof(H));
+    H.tile = t;
+    H.r0 = S.row0.p ? row0[t] : t * S.rows_per_tile;
+    H.rend = S.row0.p ? row0[t + 1] : std::min(P.nrows, (t + 1) * S.rows_per_tile);
+    H.e0 = ptr[H.r0];
+    H.e1 = ptr[H.rend];
+    H.slo = slo[t];
+    H.shi = shi[t];
+    H.blo = bptr[t];
+    H.bhi = bptr[t + 1];
+    if (H.slo < H.shi) {
+      H.rs = srs[H.slo];
+      H.nr = snr[H.slo];
+      H.nd = snd[H.slo];
+      H.sip = sip[H.slo];
+      H.svp = svp[H.slo];
+    }
+  }
+  to_dev(S.head, h, s);
+  HIPC(hipStreamSynchronize(s));
 }
 
 static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s) {

@@ -91,6 +91,16 @@ struct MmPanels {
   DBuf<int32_t> bpos;  // aligned with the schedule's tile_blk
 };
 
+// What a streamed SpMV tile needs before its first dependent load, one 64-byte record per
+// launch slot (slot k runs tile order[k]): the tile, its rows, its CSR entry range, its band
+// segment and block list ranges and its first segment's descriptor. One load of the record
+// replaces the chain order -> row bounds -> row pointers -> descriptors.
+struct TileHead {
+  int32_t tile, r0, rend, e0, e1, slo, shi, blo, bhi, rs, nr, nd, sip, pad;
+  i64 svp;
+};
+static_assert(sizeof(TileHead) == 64, "tile records are 64 bytes");
+
 struct Schedule {
   int rows_per_tile = 0;
   int ntiles = 0;
@@ -110,6 +120,7 @@ struct Schedule {
   // rows of each tile grouped by bin, stable (bin_rows, absolute row ids, tile after tile),
   // and per tile the kNumBins + 1 bin boundaries in bin_rows (empty for other schedules).
   DBuf<int32_t> bin_rows, bin_off;
+  DBuf<TileHead> head;  // streamed SpMV schedules: one record per launch slot
 };
 
 }  // namespace sable
@@ -194,6 +205,8 @@ void refresh_far_values(sable_plan_s& P, hipStream_t s);
 // fp64 copies of the far entries' values (from csr_val64), allocated on first use.
 void refresh_far_values64(sable_plan_s& P, hipStream_t s);
 void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
+// Time the plan's kernel variants and keep the fastest (op 0 SpMV, 1 SpMM with n columns).
+void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStream_t s);
 void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s);
 void launch_spmm(const sable_plan_s& P, const float* X, float* Y, int n, hipStream_t s);
 // Matrix-core mode of the tiled SpMM for the plan's variant (0 none, 1 auto split, 2 chunks).
