@@ -315,6 +315,9 @@ def cpu_baseline_spmm(A, X, rows=20000, target_s=10.0):
 def variant_kernel(v: int, far: int = 0) -> str:
     """Kernel(s) one hybrid SpMV launches for variant v ('A + B' when the far-column gather
     pass runs first)."""
+    if v >= 15:
+        k = f"k_spmv_persist<{'true' if v == 16 else 'false'}>"
+        return f"k_far_gather + {k}" if far else k
     if v >= 12:
         return "k_spmv_binned"
     if v == 11:
@@ -330,6 +333,8 @@ def variant_kernel(v: int, far: int = 0) -> str:
 
 def plain_kernel(v: int) -> str:
     """Kernel the plain CSR baseline launches for its variant v."""
+    if v >= 16:
+        return f"k_csr_persist<{'true' if v == 17 else 'false'}>"
     if v >= 13:
         return "k_csr_binned"
     if v <= 2:
@@ -413,11 +418,11 @@ def run_spmv(args, torch, sable, synth):
         sable.sable_plan_set_variant(p, 3, cf)
         sable.sable_plan_set_variant(p, 2, cp)
     elif args.autotune:
-        hc = [((3, 0), (0, v)) for v in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 13, 14)]
+        hc = [((3, 0), (0, v)) for v in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 15, 16)]
         if info["far_nnz"]:
-            hc += [((3, 1), (0, v)) for v in (0, 1, 2, 8, 9, 10)]
+            hc += [((3, 1), (0, v)) for v in (0, 1, 2, 8, 9, 10, 15, 16)]
         cold_tune(sable, p, 0, hc, f_h, 8, torch, flush)
-        cold_tune(sable, p, 2, [((2, v),) for v in range(16)], f_p, 8, torch, flush)
+        cold_tune(sable, p, 2, [((2, v),) for v in range(18)], f_p, 8, torch, flush)
     cinfo = sable.sable_plan_info(p)
     sable.sable_spmv(p, xd, y)
     err_c = sable.sable_error_norm_f64(y, ref_d)
@@ -800,6 +805,15 @@ def run_spec(args, torch, sable, synth):
             "compile_ms_median": float(np.median(comp))}
 
 
+def _small_matrix(seed):
+    """The planner's generator at n ~ logU[1e3, 3e3] (mean row length U[4, 64]): sizes where
+    the literal block search is within its budget."""
+    from paper_2407_00829_amd import planner, synth
+    n, rowlen, pi = planner.matrix_params(seed, nmin=1e3, nmax=3e3)
+    A, x = synth.gen_mixed(seed, n=n, rowlen=rowlen, pi=pi)
+    return seed, A, x
+
+
 def run_coverage(args, torch, sable, synth):
     """Block-coverage cutoff sweep, the paper's coverage-threshold table (Appendix, Tab.
     threshold) on generated matrices: --count matrices from the planner's generator (band /
@@ -817,13 +831,18 @@ def run_coverage(args, torch, sable, synth):
 
     from paper_2407_00829_amd import planner
     seeds = [300000 + args.seed * 100000 + i for i in range(args.count)]
+    literal = args.vbr_mode == "paper"
     with cf.ProcessPoolExecutor(8) as ex:
-        mats = list(ex.map(planner.make_matrix, seeds))
+        if literal:  # sizes where the literal block search of Alg. 1 / Alg. 2 is allowed
+            mats = list(ex.map(_small_matrix, seeds))
+        else:
+            mats = list(ex.map(planner.make_matrix, seeds))
     log(f"[bench] generated {len(mats)} matrices")
     n_rhs = 128
+    mode = sable.SABLE_VBR_PAPER if literal else sable.SABLE_VBR_TILED
     cov, sv, sm, times = [], [], [], []
     for i, (_, A, x) in enumerate(mats):
-        p = sable.plan_host(A, [sable.SABLE_X_VBR, sable.SABLE_X_CSR], sable.SABLE_VBR_TILED,
+        p = sable.plan_host(A, [sable.SABLE_X_VBR, sable.SABLE_X_CSR], mode,
                             sable.Thresholds(coverage_pm=0))
         q = sable.plan_host(A, [sable.SABLE_X_CSR], sable.SABLE_VBR_TILED, sable.Thresholds())
         cov.append(sable.sable_plan_info(p)["vbr_nnz"] / max(A.nnz, 1))
@@ -857,7 +876,8 @@ def run_coverage(args, torch, sable, synth):
             row[name] = {"faster": int((r > 1.0).sum()), "not_faster": int((r <= 1.0).sum()),
                          "geomean": float(np.exp(np.mean(np.log(r)))) if r.size else None}
         table.append(row)
-    return {"workload": "coverage", "matrices": len(cov), "spmm_n": n_rhs,
+    return {"workload": "coverage", "block_search": "literal" if literal else "tiled",
+            "matrices": len(cov), "spmm_n": n_rhs,
             "coverage_p10_p50_p90": [float(v) for v in np.percentile(cov, [10, 50, 90])],
             "table": table,
             "per_matrix": [[round(float(c), 4), round(float(a), 4), round(float(b), 4)]
@@ -891,6 +911,9 @@ def main():
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--variants", default="",
                     help="SpMV: 'hybrid,far_split,plain' kernel variants instead of autotuning")
+    ap.add_argument("--vbr-mode", default="tiled", choices=["tiled", "paper"],
+                    help="coverage: the block search (paper = literal Alg. 1 / Alg. 2 on "
+                         "matrices of 1e3 - 3e3 rows)")
     ap.add_argument("--spmm-variant", type=int, default=-1,
                     help="SpMM (c3): this kernel variant instead of autotuning")
     ap.add_argument("--cold-variants", default="",

@@ -134,6 +134,10 @@ typedef struct {
   uint64_t structure_hash; /* hash of A's sparsity pattern, the extractor list and the
                               thresholds: plans with equal hashes have the same formats and
                               schedules (the key of the autotuning cache) */
+  uint64_t partition_hash; /* hash of the partition itself: the format and slot of every
+                              entry and the VDIA segments and VBR blocks. Equal hashes mean
+                              the same formats with the same layout, whatever the extractor
+                              list or thresholds that produced them */
 } sable_plan_stats;
 
 /* Host buffers for sable_plan_export, sized from sable_plan_info:
@@ -274,6 +278,9 @@ sable_status sable_autotune_cache_clear(void);
  *        rows binned by length (0, 1-4, 5-8, 9-16, 17-32, 33-64, > 64 entries) within tiles of
  *        up to 256 rows, each bin's rows taken by subwaves whose width gives about 1, 2 or 4
  *        entries per lane (a wave for rows over 64 entries), bands and blocks lane per row;
+ *        15, 16 = 0 and 8 as a persistent launch (a few workgroups per CU each run many tiles
+ *        in turn, loading the next tile's record, row pointers and first entries while the
+ *        current tile computes; the same results bit for bit);
  * op 1 = SpMM: 0 tiled with matrix-core blocks (for n <= 32 the four waves split the tile's
  *        row slices, otherwise its column chunks), 1 tiled fp32, 2 one wave per row, 3 tiled
  *        with matrix-core blocks and the column-chunk split at every n, 4 tiled with the
@@ -281,7 +288,8 @@ sable_status sable_autotune_cache_clear(void);
  *        rows of X its blocks read are loaded once, 32 at a time, and multiplied in
  *        16x16x32 bf16 steps;
  * op 2 = plain CSR baseline: 0..2 streamed, 3..9 with 1..64 lanes per row, 10..12 = 0..2
- *        with non-temporal matrix loads, 13..15 = row-length bins as SpMV 12..14;
+ *        with non-temporal matrix loads, 13..15 = row-length bins as SpMV 12..14, 16, 17 = 0
+ *        and 10 as persistent launches (as SpMV 15, 16);
  * op 3 = far-column split of the streamed SpMV variants: 0 off, 1 on (when the plan has one).
  * Every variant computes the same product; each is bitwise reproducible on its own. An
  * explicit SpMM variant applies to every n (it clears the per-n autotuned choices). */
@@ -335,14 +343,18 @@ sable_status sable_mlp_train_step(float* params, float* grads, float* m, float* 
                                   void* stream, float* loss);
 
 /* Exhaustive timed search over the 15 classes (the fallback and yardstick of the learned
- * planner): plans A with every class, times its hybrid SpMV on `stream` (after one warm-up,
- * three rounds of `reps` back-to-back launches; the median per-launch average) and returns
- * the fastest plan. x[ncols], y[nrows] are scratch
- * device vectors; times_ms (host, SABLE_NCLASS entries, may be NULL) receives every class's
- * time. Classes 0..2 (CSR only) share one plan; ties go to the lower class index. */
+ * planner): plans A with every class, autotunes each plan's SpMV kernels (sable_autotune),
+ * times the chosen kernel on `stream` (after one warm-up, three rounds of `reps`
+ * back-to-back launches; the median per-launch average) and returns the fastest plan.
+ * x[ncols], y[nrows] are scratch device vectors; times_ms (host, SABLE_NCLASS entries, may be
+ * NULL) receives every class's time. Classes whose plans have the same partition_hash (for
+ * one, classes 0..2, CSR only) are timed once and share that time; ties go to the lower class
+ * index. ref_ms (host, 2 entries, may be NULL) receives, tuned and timed the same
+ * way, the plain CSR baseline (sable_csr_spmv) and the default extractor list [VDIA, VBR,
+ * CSR] with the default thresholds. */
 sable_status sable_plan_exhaustive(const sable_csr* A, const float* x, float* y, int32_t reps,
                                    void* stream, sable_plan_t* out, int32_t* best_class,
-                                   float* times_ms);
+                                   float* times_ms, float* ref_ms);
 
 /* Learned plan choice: features of A, normalised as (f - feat_mean) / feat_std (host arrays
  * of SABLE_NFEAT), MLP forward with params (device, SABLE_MLP_NPARAM), softmax. If the top

@@ -176,6 +176,47 @@ uint64_t structure_hash(const sable_csr& A, const sable_extractor* list, int nli
   return h;
 }
 
+__global__ void k_hash_owner_slot(const int8_t* __restrict__ owner, const i64* __restrict__ slot,
+                                  i64 n, unsigned long long* __restrict__ out) {
+  uint64_t acc = 0;
+  for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x)
+    acc += mix64(((uint64_t)k << 8 | (uint8_t)owner[k]) ^ mix64((uint64_t)slot[k] + 0x2545f4914f6cdd1dull));
+  atomicAdd(out, (unsigned long long)acc);
+}
+
+// Hash of the partition a plan built: which format holds each entry and where, plus the
+// segment and block descriptors that fix the stored fill. Two plans with equal hashes run the
+// same kernels over the same layout.
+uint64_t partition_hash(const sable_plan_s& P, hipStream_t s) {
+  DBuf<unsigned long long> d(6);
+  HIPC(hipMemsetAsync(d.p, 0, 6 * sizeof(unsigned long long), s));
+  auto h32 = [&](const int32_t* a, i64 n, uint64_t salt, int k) {
+    if (n <= 0) return;
+    k_hash_i32<<<grid_for(n, 256), 256, 0, s>>>(a, n, salt, d.p + k);
+    LAUNCH_CHECK();
+  };
+  if (P.nnz) {
+    k_hash_owner_slot<<<grid_for(P.nnz, 256), 256, 0, s>>>(P.owner.p, P.slot.p, P.nnz, d.p);
+    LAUNCH_CHECK();
+  }
+  h32(P.blk.p, 4 * (i64)P.nblk, 0x3c6ef372fe94f82bull, 1);
+  h32(P.idiag.p, P.nidiag, 0xa54ff53a5f1d36f1ull, 2);
+  h32(P.seg_row_start.p, P.nseg, 0x510e527fade682d1ull, 3);
+  h32(P.seg_nrows.p, P.nseg, 0x9b05688c2b3e6c1full, 4);
+  h32(P.seg_ndiags.p, P.nseg, 0x1f83d9abfb41bd6bull, 5);
+  unsigned long long h6[6];
+  HIPC(hipMemcpyAsync(h6, d.p, sizeof(h6), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  uint64_t h = 0x6a09e667f3bcc908ull;
+  auto put = [&](uint64_t v) { h = mix64_host(h ^ v) + 0x9e3779b97f4a7c15ull; };
+  for (int k = 0; k < 6; ++k) put(h6[k]);
+  put((uint64_t)(uint32_t)P.nrows << 32 | (uint32_t)P.ncols);
+  put((uint64_t)P.nnz); put((uint64_t)P.nidiag); put((uint64_t)(uint32_t)P.nseg << 32 | (uint32_t)P.nblk);
+  put((uint64_t)P.vdia_cells); put((uint64_t)P.vbr_cells); put((uint64_t)P.csr_nnz);
+  put((uint64_t)P.flags);
+  return h;
+}
+
 void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list, int nlist,
                 const sable_thresholds& th, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
@@ -232,6 +273,7 @@ void build_plan(sable_plan_s& P, const sable_csr& A, const sable_extractor* list
     for (int k = 0; k < 4; ++k) build_schedule(P, P.sched_w[k], 128 >> k, true, s);
     build_far_split(P, s);
   }
+  P.partition_hash = partition_hash(P, s);
   HIPC(hipStreamSynchronize(s));
   P.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -270,7 +312,8 @@ sable::i64 sable_plan_s::device_bytes() const {
          S->tile_blk.bytes() + S->order.bytes() + S->row0.bytes() + S->bin_rows.bytes() +
          S->bin_off.bytes() + S->head.bytes();
   }
-  b += mm_panels.kcol.bytes() + mm_panels.kptr.bytes() + mm_panels.bpos.bytes();
+  b += mm_panels.kcol.bytes() + mm_panels.kptr.bytes() + mm_panels.bpos.bytes() +
+       mm_panels.apack.bytes() + mm_panels.pan_tile.bytes() + mm_panels.pan_pos.bytes();
   b += far.ccol.bytes() + far.far_col.bytes() + far.far_src.bytes() + far.far_val.bytes() +
        far.far_prod.bytes() + far.far_val64.bytes() + far.far_prod64.bytes() + far.chunk.bytes();
   return b;
@@ -381,6 +424,7 @@ sable_status sable_plan_info(sable_plan_t p, sable_plan_stats* o) {
                       8 * p->csr_nnz + 4 * ((i64)p->nrows + 1);
     o->device_bytes = p->device_bytes();
     o->structure_hash = p->structure_hash;
+    o->partition_hash = p->partition_hash;
     o->plan_ms = p->plan_ms;
     o->spmv_variant = p->prm.spmv_variant;
     o->spmm_variant = p->prm.spmm_mode;
@@ -477,7 +521,10 @@ sable_status sable_update_values(sable_plan_t p, const float* values, void* stre
                                                             p->csr_val.p, p->a_val.p);
       LAUNCH_CHECK();
     }
-    if (p->vbr_cells && (p->flags & SABLE_F_SPLIT_BF16)) build_bf16_split(*p, s);
+    if (p->vbr_cells && (p->flags & SABLE_F_SPLIT_BF16)) {
+      build_bf16_split(*p, s);
+      pack_mm_panels(*p, s);
+    }
     refresh_far_values(*p, s);
   });
 }

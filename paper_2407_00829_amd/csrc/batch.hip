@@ -1,14 +1,17 @@
 // Batched persistent execution of many plans, captured in a hipGraph.
 //
-// Work units are (item, tile) pairs laid out item by item, SpMV items and SpMM items in two
-// lists. Two persistent kernels, one per list, each with a grid of every CU times its
+// Work units are (item, tile) pairs laid out item by item, in seven lists: SpMV items by
+// streamed tile (three tile heights, with and without non-temporal loads) and SpMM items.
+// One persistent kernel per non-empty list, each with a grid of every CU times its
 // resident workgroups, pull units from their own atomic counter; a unit runs exactly the tile
 // body of the standalone product, so each item's result is bitwise equal to its standalone
-// launch with the same kernel (SpMV: the 256-row streamed tile, variant 0; SpMM: the fused
-// tile in the plan's matrix-core mode, the LDS-staged panel tile included). Keeping the two apart lets each run at the occupancy
-// of its standalone kernel. The last unit of an item stamps the GPU wall clock. A reset kernel
-// (no memset nodes) clears the counters and stamps the batch start; the three kernels are
-// captured once and replayed.
+// launch with the same kernel (SpMV: the streamed tile of the plan's tuned streamed variant,
+// 256, 512 or 1024 rows, with or without non-temporal loads, and the 256-row tile for the
+// other variants; SpMM: the fused tile in the plan's matrix-core mode, the LDS-staged panel
+// tile included). Keeping the lists apart lets each kernel run at the occupancy of its
+// standalone kernel. The last unit of an item stamps the GPU wall clock. A reset kernel (no
+// memset nodes) clears the counters and stamps the batch start; the kernels are captured
+// once and replayed.
 #include <algorithm>
 
 #include "exec.h"
@@ -25,13 +28,14 @@ struct BatchItemDev {
 
 namespace {
 
+constexpr int kBatchCounters = 7;  // one per work list
+
 __global__ void k_batch_reset(unsigned* __restrict__ counter, unsigned* __restrict__ done,
                               const BatchItemDev* __restrict__ items, int count,
                               unsigned long long* __restrict__ stamps) {
   __shared__ unsigned long long t0;
   if (threadIdx.x == 0) {
-    counter[0] = 0;
-    counter[1] = 0;
+    for (int k = 0; k < kBatchCounters; ++k) counter[k] = 0;
     t0 = wall_clock64();
     stamps[count] = t0;
   }
@@ -42,12 +46,12 @@ __global__ void k_batch_reset(unsigned* __restrict__ counter, unsigned* __restri
   }
 }
 
-constexpr int kBatchSpmvLds = kCsrChunk + kSpmvThreads;  // spmv_tile_stream<1>
 constexpr int kBatchSpmmLds = kMmRows * kMmCols + kMmBlkStage * kBlkDesc;
 static_assert(kBatchSpmmLds * 4 >= kPanLdsBytes, "the panel tile fits the SpMM units' LDS");
 
-// Units of one list: list[k] is the item of the k-th entry, off[k] its first unit.
-template <int OP>
+// Units of one list: list[k] is the item of the k-th entry, off[k] its first unit. OP 0: SpMV
+// units of the streamed tile with RPT rows per thread (NT: non-temporal loads); OP 1: SpMM.
+template <int OP, int RPT = 1, bool NT = false>
 __device__ __forceinline__ void batch_units(const PlanView* __restrict__ views,
                                             const BatchItemDev* __restrict__ items,
                                             const int32_t* __restrict__ list,
@@ -74,7 +78,7 @@ __device__ __forceinline__ void batch_units(const PlanView* __restrict__ views,
     const PlanView& P = views[it];
     int local = (int)(u - off[lo]);
     if constexpr (OP == 0) {
-      spmv_tile_stream<1>(P, local, I.x, I.y, lds);  // local = launch slot
+      spmv_tile_stream<RPT, NT>(P, local, I.x, I.y, lds);  // local = launch slot
     } else {
       int rt = local % I.units_per_col;
       const int cc = local / I.units_per_col;
@@ -90,6 +94,7 @@ __device__ __forceinline__ void batch_units(const PlanView* __restrict__ views,
   }
 }
 
+template <int RPT, bool NT>
 __global__ __launch_bounds__(256) void k_batch_spmv(const PlanView* __restrict__ views,
                                                     const BatchItemDev* __restrict__ items,
                                                     const int32_t* __restrict__ list,
@@ -97,9 +102,23 @@ __global__ __launch_bounds__(256) void k_batch_spmv(const PlanView* __restrict__
                                                     i64 total, unsigned* __restrict__ counter,
                                                     unsigned* __restrict__ done,
                                                     unsigned long long* __restrict__ stamps) {
-  __shared__ float lds[kBatchSpmvLds];
-  batch_units<0>(views, items, list, off, nlist, total, counter, done, stamps, lds);
+  __shared__ float lds[kCsrChunk + kSpmvThreads * RPT];
+  batch_units<0, RPT, NT>(views, items, list, off, nlist, total, counter, done, stamps, lds);
 }
+
+// SpMV group g of a batch: the streamed tile with 1, 2 or 4 rows per thread (g % 3), with
+// non-temporal loads for g >= 3; the plan's tuned streamed variant picks its group.
+constexpr int kSpmvGroups = 6;
+inline int spmv_group(int variant) {
+  if (variant >= 0 && variant <= 2) return variant;
+  if (variant >= 8 && variant <= 10) return 3 + (variant - 8);
+  return 0;  // W-lanes, binned and specialized variants: the 256-row streamed tile
+}
+typedef void (*BatchKernel)(const PlanView*, const BatchItemDev*, const int32_t*, const i64*, int,
+                            i64, unsigned*, unsigned*, unsigned long long*);
+const BatchKernel kSpmvKernels[kSpmvGroups] = {k_batch_spmv<1, false>, k_batch_spmv<2, false>,
+                                               k_batch_spmv<4, false>, k_batch_spmv<1, true>,
+                                               k_batch_spmv<2, true>, k_batch_spmv<4, true>};
 
 __global__ __launch_bounds__(256, 3) void k_batch_spmm(const PlanView* __restrict__ views,
                                                        const BatchItemDev* __restrict__ items,
@@ -120,8 +139,10 @@ struct sable_batch_s {
   int count = 0;
   sable::DBuf<sable::PlanView> views;
   sable::DBuf<sable::BatchItemDev> items;
-  sable::DBuf<int32_t> list[2];     // SpMV items, SpMM items
-  sable::DBuf<sable::i64> off[2];   // first unit of each list entry, total at the end
+  // work lists: SpMV items by streamed-tile group (6), then SpMM items
+  static constexpr int kLists = 7;
+  sable::DBuf<int32_t> list[kLists];
+  sable::DBuf<sable::i64> off[kLists];  // first unit of each list entry, total at the end
   sable::DBuf<unsigned> counter, done;
   sable::DBuf<unsigned long long> stamps;
   hipStream_t cap = nullptr;
@@ -135,6 +156,8 @@ struct sable_batch_s {
     if (cap) (void)hipStreamDestroy(cap);
   }
 };
+
+static_assert(sable_batch_s::kLists == sable::kBatchCounters, "one work counter per list");
 
 using namespace sable;
 
@@ -161,8 +184,10 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
     B->count = count;
     std::vector<PlanView> hv(count);
     std::vector<BatchItemDev> hi(count);
-    std::vector<int32_t> lists[2];
-    std::vector<i64> offs[2] = {{0}, {0}};
+    constexpr int NL = sable_batch_s::kLists;
+    std::vector<int32_t> lists[NL];
+    std::vector<i64> offs[NL];
+    for (auto& o : offs) o.push_back(0);
     for (int i = 0; i < count; ++i) {
       const sable_plan_s& P = *plans[i];
       const sable_batch_item& it = items[i];
@@ -173,9 +198,11 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
       d.x = it.x;
       d.y = it.y;
       i64 units = 0;
+      int li = kSpmvGroups;  // work list of the item
       if (P.nrows > 0) {
         if (it.op == 0) {
-          hv[i] = make_view(P, P.sched[0], false);
+          li = spmv_group(P.prm.spmv_variant);
+          hv[i] = make_view(P, P.sched[li % 3], false);
           units = hv[i].ntiles;
         } else {
           hv[i] = make_view(P, P.sched_mm, false);
@@ -189,20 +216,21 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
       d.units = (int)units;
       hi[i] = d;
       if (units) {
-        lists[it.op].push_back(i);
-        offs[it.op].push_back(offs[it.op].back() + units);
+        lists[li].push_back(i);
+        offs[li].push_back(offs[li].back() + units);
       }
     }
-    const i64 total[2] = {offs[0].back(), offs[1].back()};
-    if (total[0] + total[1] > (i64)UINT32_MAX / 2) SB_THROW(SABLE_ERR_TOO_LARGE, "too many work units");
+    i64 total[NL], all = 0;
+    for (int k = 0; k < NL; ++k) all += (total[k] = offs[k].back());
+    if (all > (i64)UINT32_MAX / 2) SB_THROW(SABLE_ERR_TOO_LARGE, "too many work units");
     to_dev(B->views, hv, s);
     to_dev(B->items, hi, s);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < NL; ++k) {
       lists[k].push_back(-1);  // never read: keeps the arrays non-empty
       to_dev(B->list[k], lists[k], s);
       to_dev(B->off[k], offs[k], s);
     }
-    B->counter.alloc(2);
+    B->counter.alloc(NL);
     B->done.alloc(count);
     B->stamps.alloc(count + 1);
     HIPC(hipStreamSynchronize(s));
@@ -212,23 +240,24 @@ sable_status sable_batch_create(const sable_plan_t* plans, const sable_batch_ite
     HIPC(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     B->tick_hz = (double)khz * 1e3;
     // resident workgroups per CU of each kernel (registers and LDS) size its grid
-    int per_cu[2] = {0, 0};
-    HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[0], k_batch_spmv, 256, 0));
-    HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[1], k_batch_spmm, 256, 0));
-    unsigned grid[2];
-    for (int k = 0; k < 2; ++k)
-      grid[k] = (unsigned)std::max<i64>(1, std::min<i64>(total[k], (i64)cus * std::max(1, per_cu[k])));
+    auto grid_of = [&](const void* kern, i64 units) {
+      int per_cu = 0;
+      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
+      return (unsigned)std::max<i64>(1, std::min<i64>(units, (i64)cus * std::max(1, per_cu)));
+    };
     HIPC(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
     HIPC(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
     k_batch_reset<<<1, 256, 0, B->cap>>>(B->counter.p, B->done.p, B->items.p, count, B->stamps.p);
-    if (total[0])
-      k_batch_spmv<<<grid[0], 256, 0, B->cap>>>(B->views.p, B->items.p, B->list[0].p, B->off[0].p,
-                                                (int)lists[0].size() - 1, total[0], B->counter.p,
-                                                B->done.p, B->stamps.p);
-    if (total[1])
-      k_batch_spmm<<<grid[1], 256, 0, B->cap>>>(B->views.p, B->items.p, B->list[1].p, B->off[1].p,
-                                                (int)lists[1].size() - 1, total[1], B->counter.p + 1,
-                                                B->done.p, B->stamps.p);
+    for (int g = 0; g < kSpmvGroups; ++g)
+      if (total[g])
+        kSpmvKernels[g]<<<grid_of((const void*)kSpmvKernels[g], total[g]), 256, 0, B->cap>>>(
+            B->views.p, B->items.p, B->list[g].p, B->off[g].p, (int)lists[g].size() - 1, total[g],
+            B->counter.p + g, B->done.p, B->stamps.p);
+    if (total[kSpmvGroups])
+      k_batch_spmm<<<grid_of((const void*)k_batch_spmm, total[kSpmvGroups]), 256, 0, B->cap>>>(
+          B->views.p, B->items.p, B->list[kSpmvGroups].p, B->off[kSpmvGroups].p,
+          (int)lists[kSpmvGroups].size() - 1, total[kSpmvGroups], B->counter.p + kSpmvGroups,
+          B->done.p, B->stamps.p);
     hipError_t ce = hipStreamEndCapture(B->cap, &B->graph);
     if (ce != hipSuccess) SB_THROW(SABLE_ERR_HIP, "stream capture: %s", hipGetErrorString(ce));
     HIPC(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));

@@ -44,6 +44,7 @@ struct PlanView {
   const int32_t* mm_kcol;
   const int32_t* mm_kptr;
   const int32_t* mm_bpos;
+  const uint16_t* mm_apack;
 };
 
 // Value arrays of the view for the executor's value type.
@@ -224,8 +225,7 @@ struct CsrFlight {
 };
 
 template <class T, bool NT, int U>
-__device__ __forceinline__ void csr_issue(const PlanView& P, int e0, int e_end,
-                                          const T* __restrict__ x, CsrFlight<T, U>& f) {
+__device__ __forceinline__ void csr_issue_idx(const PlanView& P, int e0, int e_end, CsrFlight<T, U>& f) {
   const T* val = Vals<T>::csr(P);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -233,9 +233,20 @@ __device__ __forceinline__ void csr_issue(const PlanView& P, int e0, int e_end,
     f.j[u] = ld<NT>(P.csr_col + k);
     f.a[u] = ld<NT>(val + k);
   }
+}
+
+template <class T, int U>
+__device__ __forceinline__ void csr_issue_x(const PlanView& P, const T* __restrict__ x, CsrFlight<T, U>& f) {
   const T* fp = Vals<T>::far(P) ? Vals<T>::far(P) : x;  // stored far-column products
 #pragma unroll
   for (int u = 0; u < U; ++u) f.v[u] = *(f.j[u] >= 0 ? x + f.j[u] : fp + (-1 - f.j[u]));
+}
+
+template <class T, bool NT, int U>
+__device__ __forceinline__ void csr_issue(const PlanView& P, int e0, int e_end,
+                                          const T* __restrict__ x, CsrFlight<T, U>& f) {
+  csr_issue_idx<T, NT, U>(P, e0, e_end, f);
+  csr_issue_x<T, U>(P, x, f);
 }
 
 template <class T, int U>
@@ -247,35 +258,51 @@ __device__ __forceinline__ void csr_finish(const CsrFlight<T, U>& f, int e0, int
   }
 }
 
-// slot: the launch slot (the tile is the slot's record's).
-template <int RPT, bool NT = false, class T = float>
-__device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int slot,
-                                                 const T* __restrict__ x,
-                                                 T* __restrict__ y, float* __restrict__ lds) {
+// A streamed tile between the arrival of its record and its body: the row pointers of this
+// thread's rows and the first CSR pass's columns and values (loads issued, x not yet read).
+template <int RPT, class T>
+struct StreamTile {
+  TileHead H;
+  int kb[RPT], ke[RPT];
+  CsrFlight<T, CsrPass<RPT>::U> fl;
+};
+
+// The loads of a tile that need only its record.
+template <int RPT, bool NT, class T>
+__device__ __forceinline__ void stream_prefetch(const PlanView& P, StreamTile<RPT, T>& S) {
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = S.H.r0 + (int)threadIdx.x + kSpmvThreads * q;
+    S.kb[q] = r < S.H.rend ? P.csr_ptr[r] : 0;
+    S.ke[q] = r < S.H.rend ? P.csr_ptr[r + 1] : 0;
+  }
+  if (S.H.e0 < S.H.e1) csr_issue_idx<T, NT, CsrPass<RPT>::U>(P, S.H.e0, S.H.e1, S.fl);
+}
+
+// The rest of the tile: the first pass's gathers of x, bands, blocks, CSR, stores.
+template <int RPT, bool NT, class T>
+__device__ __forceinline__ void stream_body(const PlanView& P, StreamTile<RPT, T>& S,
+                                            const T* __restrict__ x, T* __restrict__ y,
+                                            float* __restrict__ lds) {
   constexpr int RT = kSpmvThreads * RPT;
   constexpr int U = CsrPass<RPT>::U;
   constexpr int kPass = U * kSpmvThreads;
   T* prod = reinterpret_cast<T*>(lds);  // kPass products (lds holds kCsrChunk + RT values of T)
   T* part = prod + kCsrChunk;           // RT block partials
-  const TileHead H = P.tile_head[slot];  // uniform: one scalar load of the whole record
+  const TileHead& H = S.H;
   const int r0 = H.r0, rend = H.rend;
   const int t = threadIdx.x;
-  // 0. independent loads, then the first CSR pass
+  // 0. the first CSR pass's gathers
   const int e_begin = H.e0, e_end = H.e1;
   const int slo = H.slo, shi = H.shi;
   const int blo = H.blo, bhi = H.bhi;
-  int kb[RPT], ke[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = r0 + t + kSpmvThreads * q;
-    kb[q] = r < rend ? P.csr_ptr[r] : 0;
-    ke[q] = r < rend ? P.csr_ptr[r + 1] : 0;
-  }
+  int(&kb)[RPT] = S.kb;
+  int(&ke)[RPT] = S.ke;
   int rs = H.rs, nr = H.nr, nd = H.nd;
   i64 svp = H.svp;
   int sip = H.sip;
-  CsrFlight<T, U> fl;
-  if (e_begin < e_end) csr_issue<T, NT, U>(P, e_begin, e_end, x, fl);
+  CsrFlight<T, U>& fl = S.fl;
+  if (e_begin < e_end) csr_issue_x<T, U>(P, x, fl);
 
   T acc[RPT];
 #pragma unroll
@@ -395,6 +422,17 @@ __device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int slot,
     const int r = r0 + t + kSpmvThreads * q;
     if (r < rend) y[r] = acc[q] + cs[q];
   }
+}
+
+// slot: the launch slot (the tile is the slot's record's).
+template <int RPT, bool NT = false, class T = float>
+__device__ __forceinline__ void spmv_tile_stream(const PlanView& P, int slot,
+                                                 const T* __restrict__ x,
+                                                 T* __restrict__ y, float* __restrict__ lds) {
+  StreamTile<RPT, T> S;
+  S.H = P.tile_head[slot];  // uniform: one scalar load of the whole record
+  stream_prefetch<RPT, NT, T>(P, S);
+  stream_body<RPT, NT, T>(P, S, x, y, lds);
 }
 
 // ---- SpMV tile body, row-length bins ----------------------------------------------------

@@ -53,6 +53,7 @@ PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool fa
     v.mm_kcol = P.mm_panels.kcol.p;
     v.mm_kptr = P.mm_panels.kptr.p;
     v.mm_bpos = P.mm_panels.bpos.p;
+    v.mm_apack = P.mm_panels.apack.p;
   }
   if (far && P.far.npanel && P.prm.far_split) {
     v.csr_col = P.far.ccol.p;
@@ -225,6 +226,51 @@ __global__ __launch_bounds__(256) void k_spmv_stream(PlanView P, const float* __
   spmv_tile_stream<RPT, NT>(P, slot, x, y, lds);
 }
 
+// Persistent streamed SpMV (256-row tiles): nw workgroups per XCD; workgroup j of XCD xs
+// takes the launch slots j, j + nw, ... of that XCD's contiguous run of slots. While one
+// tile's body runs, the next tile's record is loaded; its row pointers and first CSR pass are
+// issued as soon as the body's stores are, so each tile starts with only its gathers of x
+// outstanding instead of the chain record -> row pointers -> entries -> x. Every tile runs
+// the streamed body unchanged (results equal the one-tile-per-workgroup launch bit for bit).
+template <bool NT>
+__device__ __forceinline__ void spmv_persist(const PlanView& P, const float* __restrict__ x,
+                                             float* __restrict__ y, int nw, float* lds) {
+  const int per = (P.ntiles + 7) >> 3;
+  const int xs = blockIdx.x & 7;
+  const int s1 = min(P.ntiles, (xs + 1) * per);
+  int slot = xs * per + (int)(blockIdx.x >> 3);
+  if (slot >= s1) return;
+  StreamTile<1, float> S;
+  S.H = P.tile_head[slot];
+  stream_prefetch<1, NT, float>(P, S);
+  for (;;) {
+    const int next = slot + nw;
+    const bool more = next < s1;
+    TileHead Hn;
+    if (more) Hn = P.tile_head[next];
+    stream_body<1, NT, float>(P, S, x, y, lds);
+    if (!more) break;
+    S.H = Hn;
+    stream_prefetch<1, NT, float>(P, S);
+    slot = next;
+  }
+}
+
+template <bool NT>
+__global__ __launch_bounds__(256) void k_spmv_persist(PlanView P, const float* __restrict__ x,
+                                                     float* __restrict__ y, int nw) {
+  __shared__ float lds[kCsrChunk + kSpmvThreads];
+  spmv_persist<NT>(P, x, y, nw, lds);
+}
+
+// The plain CSR baseline's persistent variants (the same body over the input as one CSR).
+template <bool NT>
+__global__ __launch_bounds__(256) void k_csr_persist(PlanView P, const float* __restrict__ x,
+                                                    float* __restrict__ y, int nw) {
+  __shared__ float lds[kCsrChunk + kSpmvThreads];
+  spmv_persist<NT>(P, x, y, nw, lds);
+}
+
 // Row-length bins: subwave widths per bin (u = log2 of entries per lane).
 __global__ __launch_bounds__(256) void k_spmv_binned(PlanView P, const int32_t* __restrict__ brow,
                                                     const int32_t* __restrict__ boff, int u,
@@ -353,6 +399,41 @@ __global__ __launch_bounds__(kMmThreads, 4) void k_spmm_tile_valu(PlanView P, co
   if (t >= ntile) return;
   if (P.tile_order) t = P.tile_order[t];
   spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, 0);
+}
+
+// One workgroup per panel: the tile's block cells that fall in the panel's 32 list positions,
+// as a zero-filled 64 x 32 hi plane and lo plane (built in LDS, then written out whole).
+__global__ __launch_bounds__(256) void k_pack_panels(PlanView P, const int32_t* __restrict__ pan_tile,
+                                                    const int32_t* __restrict__ pan_pos,
+                                                    uint16_t* __restrict__ apack) {
+  __shared__ __align__(16) uint16_t pl[2 * kMmRows * kPanK];
+  const i64 g = blockIdx.x;
+  const int tile = pan_tile[g], pj = pan_pos[g];
+  const int r0 = tile * kMmRows, rend = min(r0 + kMmRows, P.nrows);
+  for (int i = threadIdx.x; i < 2 * kMmRows * kPanK / 4; i += blockDim.x)  // both planes
+    reinterpret_cast<uint64_t*>(pl)[i] = 0ull;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q = P.tile_blk_ptr[tile] + wave; q < P.tile_blk_ptr[tile + 1]; q += 4) {
+    const int b = P.tile_blk[q], p0 = P.mm_bpos[q];
+    const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
+    const int w = P.blk[4 * b + 3] - P.blk[4 * b + 2];
+    const int ka = max(p0, pj), kz = min(p0 + w, pj + kPanK);
+    const int ra = max(br0, r0), rz = min(br1, rend);
+    if (ka >= kz || ra >= rz) continue;
+    const int nk = kz - ka, cells = (rz - ra) * nk, w4 = (w + 3) & ~3;
+    const uint32_t* src = P.vbr_mma + P.blk_mma_ptr[b];
+    for (int c = lane; c < cells; c += 64) {
+      const int r = ra + c / nk, kk = ka + c % nk;
+      const uint32_t word = src[(i64)(r - br0) * w4 + (kk - p0)];
+      pl[(r - r0) * kPanK + (kk - pj)] = (uint16_t)(word & 0xffffu);
+      pl[kMmRows * kPanK + (r - r0) * kPanK + (kk - pj)] = (uint16_t)(word >> 16);
+    }
+  }
+  __syncthreads();
+  uint4* out = reinterpret_cast<uint4*>(apack + g * (2 * kMmRows * kPanK));
+  for (int i = threadIdx.x; i < 2 * kMmRows * kPanK / 8; i += blockDim.x)
+    out[i] = reinterpret_cast<const uint4*>(pl)[i];
 }
 
 // Blocks on matrix cores from LDS-staged panels (16x16x32 bf16 steps).
@@ -648,10 +729,45 @@ SABLE_STREAM_LAUNCH(k_spmv_stream)
 SABLE_STREAM_LAUNCH(k_csr_stream)
 #undef SABLE_STREAM_LAUNCH
 
+// Workgroups per XCD of a persistent kernel: its resident workgroups per CU times the CUs of
+// one XCD (queried once per kernel; the device's CU count / 8), at most the XCD's slots.
+template <bool NT, bool PLAIN>
+static int persist_nw(int ntiles) {
+  static const int per_xcd = [] {
+    const void* kern = PLAIN ? (const void*)k_csr_persist<NT> : (const void*)k_spmv_persist<NT>;
+    int occ = 0, dev = 0, cus = 0;
+    HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kSpmvThreads, 0));
+    HIPC(hipGetDevice(&dev));
+    HIPC(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return std::max(1, occ) * std::max(1, cus / 8);
+  }();
+  return std::max(1, std::min(per_xcd, (ntiles + 7) / 8));
+}
+
+template <bool NT, bool PLAIN>
+static void launch_persist(const PlanView& v, const float* x, float* y, hipStream_t s) {
+  const int nw = persist_nw<NT, PLAIN>(v.ntiles);
+  if (PLAIN) k_csr_persist<NT><<<(unsigned)(8 * nw), kSpmvThreads, 0, s>>>(v, x, y, nw);
+  else k_spmv_persist<NT><<<(unsigned)(8 * nw), kSpmvThreads, 0, s>>>(v, x, y, nw);
+  LAUNCH_CHECK();
+}
+
 void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
   const int var = P.prm.spmv_variant;
   if (var == 11) {
     launch_spmv_spec(P, x, y, s);
+    return;
+  }
+  if (var >= 15) {  // persistent streamed tiles (with the far-column pass when enabled)
+    const PlanView v = make_view(P, P.sched[0], false, true);
+    if (v.far_prod) {
+      k_far_gather<float><<<(unsigned)(8 * P.far.per_xcd), kFarThreads, 0, s>>>(
+          P.far.chunk.p, P.far.per_xcd, P.ncols, P.far.far_col.p, P.far.far_val.p, x,
+          P.far.far_prod.p);
+      LAUNCH_CHECK();
+    }
+    if (var == 16) launch_persist<true, false>(v, x, y, s);
+    else launch_persist<false, false>(v, x, y, s);
     return;
   }
   if (var >= 12) {
@@ -689,6 +805,12 @@ void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s)
 
 void launch_spmv_plain(const sable_plan_s& P, const float* x, float* y, hipStream_t s) {
   const int var = P.prm.plain_variant;
+  if (var >= 16) {
+    const PlanView v = make_view(P, P.sched_plain[0], true);
+    if (var == 17) launch_persist<true, true>(v, x, y, s);
+    else launch_persist<false, true>(v, x, y, s);
+    return;
+  }
   if (var >= 13) {
     const Schedule& S = P.sched_plain[0];
     const PlanView v = make_view(P, S, true);
@@ -756,6 +878,10 @@ void build_mm_panels(sable_plan_s& P, hipStream_t s) {
   M.kcol.reset();
   M.kptr.reset();
   M.bpos.reset();
+  M.apack.reset();
+  M.pan_tile.reset();
+  M.pan_pos.reset();
+  M.npanels = 0;
   const Schedule& S = P.sched_mm;
   if (!P.vbr_mma.p || P.nblk == 0 || S.ntiles == 0) return;
   std::vector<int32_t> blk, tptr, tblk;
@@ -784,6 +910,29 @@ void build_mm_panels(sable_plan_s& P, hipStream_t s) {
   to_dev(M.kcol, kcol, s);
   to_dev(M.kptr, kptr, s);
   to_dev(M.bpos, bpos, s);
+  std::vector<int32_t> ptile, ppos;
+  for (int t = 0; t < S.ntiles; ++t)
+    for (int k = kptr[t]; k < kptr[t + 1]; k += kPanK) {
+      ptile.push_back(t);
+      ppos.push_back(k - kptr[t]);
+    }
+  M.npanels = (i64)ptile.size();
+  to_dev(M.pan_tile, ptile, s);
+  to_dev(M.pan_pos, ppos, s);
+  M.apack.alloc((size_t)M.npanels * 2 * kMmRows * kPanK);
+  pack_mm_panels(P, s);
+}
+
+void pack_mm_panels(sable_plan_s& P, hipStream_t s) {
+  MmPanels& M = P.mm_panels;
+  if (!M.npanels || !P.vbr_mma.p) return;
+  const PlanView v = make_view(P, P.sched_mm, false);
+  for (i64 g0 = 0; g0 < M.npanels; g0 += (1 << 30)) {  // grid.x limit
+    const unsigned nb = (unsigned)std::min<i64>(M.npanels - g0, 1 << 30);
+    k_pack_panels<<<nb, 256, 0, s>>>(v, M.pan_tile.p + g0, M.pan_pos.p + g0,
+                                     M.apack.p + g0 * 2 * kMmRows * kPanK);
+    LAUNCH_CHECK();
+  }
   HIPC(hipStreamSynchronize(s));
 }
 

@@ -89,6 +89,14 @@ struct MmPanels {
   DBuf<int32_t> kcol;  // tile t: kcol[kptr[t] .. kptr[t + 1])
   DBuf<int32_t> kptr;  // ntiles + 1 offsets, multiples of 32
   DBuf<int32_t> bpos;  // aligned with the schedule's tile_blk
+  // The A operand of every panel, packed at plan time from the split-bf16 words: panel g
+  // (g = kptr[t] / 32 + j for panel j of tile t) is a 64 x 32 hi plane then a 64 x 32 lo plane
+  // (bf16, row-major, zero where no block cell falls), 8 KB, so the SpMM loads it with two
+  // 16-byte loads per thread instead of gathering cells. pan_tile / pan_pos: tile and
+  // tile-relative first list position of each panel.
+  DBuf<uint16_t> apack;
+  DBuf<int32_t> pan_tile, pan_pos;
+  i64 npanels = 0;
 };
 
 // What a streamed SpMV tile needs before its first dependent load, one 64-byte record per
@@ -169,6 +177,7 @@ struct sable_plan_s {
   uint32_t flags = 0;
   double plan_ms = 0.0;
   uint64_t structure_hash = 0;  // pattern of A, extractor list, thresholds (autotuning cache key)
+  uint64_t partition_hash = 0;  // owner and slot of every entry, VDIA segments, VBR blocks
   // run-time specialized SpMV (hipRTC module and kernel; null until sable_plan_specialize)
   void* spec_module = nullptr;
   void* spec_func = nullptr;
@@ -199,6 +208,8 @@ void build_schedule(sable_plan_s& P, Schedule& S, int rows_per_tile, bool with_f
                     hipStream_t s, bool col_order = false, bool balance = false);
 void build_bf16_split(sable_plan_s& P, hipStream_t s);
 void build_mm_panels(sable_plan_s& P, hipStream_t s);
+// (Re)pack the panels' A operands from the split-bf16 words (after a value refresh).
+void pack_mm_panels(sable_plan_s& P, hipStream_t s);
 void build_bins(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s);
 void build_far_split(sable_plan_s& P, hipStream_t s);
 void refresh_far_values(sable_plan_s& P, hipStream_t s);

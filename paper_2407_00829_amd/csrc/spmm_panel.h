@@ -6,8 +6,10 @@
 //       * the 32 rows of X it names are loaded once with 16-byte loads, split into bf16 hi
 //         and lo parts (hardware round-to-nearest-even) and stored transposed in LDS, k
 //         contiguous per column, the layout of the B operand of v_mfma_f32_16x16x32_bf16;
-//       * the tile's block cells that fall in the panel are copied from the plan's packed
-//         hi | lo words (the split done at plan time) into a zeroed 64 x 32 A operand in LDS;
+//       * the panel's A operand, the tile's block cells that fall in it as a zero-filled
+//         64 x 32 hi plane and lo plane packed at plan time from the split-bf16 words, is
+//         copied into LDS with two 16-byte loads per thread;
+//       * both loads of the next panel are issued before this panel's products run;
 //       * each wave then runs, for its 16-column chunks and 16-row slices, three
 //         16x16x32 products hi*hi + hi*lo + lo*hi with fp32 accumulation in registers.
 //     One k step of 32 covers a C3 6x18 strip with room to spare, and each X row a tile needs
@@ -199,16 +201,20 @@ __device__ __forceinline__ void spmm_rows_quad(const PlanView& P, int tile, int 
   }
 }
 
-// Stage the panel's X rows (list positions kp .. kp + 31 of kcol, -1 = none) as bf16 hi / lo
-// in LDS, transposed: plane[col * kPanLd + k]. Thread t takes k = 4 (t % 8) .. + 3 and
-// columns 4 (t / 8) .. + 3 of the chunk (the eight lanes of one column group write 64
-// consecutive bytes of a column, so a half wave's 8-byte stores cover all banks once);
-// columns >= nc are stored as 0.
-__device__ __forceinline__ void stage_x_panel(const int32_t* __restrict__ kcol, const float* __restrict__ X,
-                                              int n, int cb, int nc, uint16_t* bh, uint16_t* bl) {
+// The panel's X rows (list positions kp .. kp + 31 of kcol, -1 = none) as bf16 hi / lo in
+// LDS, transposed: plane[col * kPanLd + k]. Thread t takes k = 4 (t % 8) .. + 3 and columns
+// 4 (t / 8) .. + 3 of the chunk (the eight lanes of one column group write 64 consecutive
+// bytes of a column, so a half wave's 8-byte stores cover all banks once); columns >= nc are
+// stored as 0. load_x_panel reads the values into registers (so they can be in flight while
+// the previous panel's products run), store_x_panel splits and writes them.
+struct XPanel {
+  float v[4][4];  // [k][column]
+};
+
+__device__ __forceinline__ void load_x_panel(const int32_t* __restrict__ kcol, const float* __restrict__ X,
+                                             int n, int cb, int nc, XPanel& xp) {
   const int t = threadIdx.x;
   const int k0 = 4 * (t & 7), c0 = 4 * (t >> 3);
-  float v[4][4];  // [k][column]
   int row[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) row[kk] = kcol[k0 + kk];
@@ -218,18 +224,23 @@ __device__ __forceinline__ void stage_x_panel(const int32_t* __restrict__ kcol, 
       const float4 q = row[kk] >= 0
                            ? *reinterpret_cast<const float4*>(X + (i64)row[kk] * n + cb + c0)
                            : make_float4(0.f, 0.f, 0.f, 0.f);
-      v[kk][0] = q.x; v[kk][1] = q.y; v[kk][2] = q.z; v[kk][3] = q.w;
+      xp.v[kk][0] = q.x; xp.v[kk][1] = q.y; xp.v[kk][2] = q.z; xp.v[kk][3] = q.w;
     }
   } else {
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        v[kk][c] = (row[kk] >= 0 && c0 + c < nc) ? X[(i64)row[kk] * n + cb + c0 + c] : 0.f;
+        xp.v[kk][c] = (row[kk] >= 0 && c0 + c < nc) ? X[(i64)row[kk] * n + cb + c0 + c] : 0.f;
   }
+}
+
+__device__ __forceinline__ void store_x_panel(const XPanel& xp, uint16_t* bh, uint16_t* bl) {
+  const int t = threadIdx.x;
+  const int k0 = 4 * (t & 7), c0 = 4 * (t >> 3);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const float col4[4] = {v[0][c], v[1][c], v[2][c], v[3][c]};
+    const float col4[4] = {xp.v[0][c], xp.v[1][c], xp.v[2][c], xp.v[3][c]};
     bf16x4_t h, l;
     split4(col4, h, l);
     *reinterpret_cast<bf16x4_t*>(bh + (c0 + c) * kPanLd + k0) = h;
@@ -239,6 +250,8 @@ __device__ __forceinline__ void stage_x_panel(const int32_t* __restrict__ kcol, 
 
 // Rows [r0, r0 + kMmRows) x columns [cb, cb + nc) of Y for tile `tile` of the view's 64-row
 // schedule; lds holds kPanLdsBytes.
+static_assert(kMmThreads * 8 == kMmRows * kPanK, "one 16-byte load per thread fills a 64 x 32 plane");
+
 __device__ __forceinline__ void spmm_tile_panel(const PlanView& P, int tile, int cb, int n,
                                                 const float* __restrict__ X, float* __restrict__ Y,
                                                 uint8_t* __restrict__ lds) {
@@ -263,41 +276,29 @@ __device__ __forceinline__ void spmm_tile_panel(const PlanView& P, int tile, int
   // no panels: a plan without blocks (bands and CSR only)
   const int kb = P.mm_kptr ? __builtin_amdgcn_readfirstlane(P.mm_kptr[tile]) : 0;
   const int ke = P.mm_kptr ? __builtin_amdgcn_readfirstlane(P.mm_kptr[tile + 1]) : 0;
-  const int blo = P.tile_blk_ptr[tile], bhi = P.tile_blk_ptr[tile + 1];
-  int qa = blo, qb = blo;  // tile blocks (ordered by first list position) that may meet the panel
+  // operands of panel j: the packed A planes (two 16-byte loads per thread: row t / 4,
+  // columns 8 (t % 4) .. + 7 of each plane) and the 32 rows of X; both for the next panel load
+  // while this panel's products run
+  const uint4* apk = reinterpret_cast<const uint4*>(P.mm_apack) + (i64)(kb / kPanK) * (2 * kMmRows * kPanK / 8);
+  const int at = threadIdx.x;
+  const int arow = at >> 2, acol = 8 * (at & 3);
+  uint4 aw_h = make_uint4(0u, 0u, 0u, 0u), aw_l = aw_h;
+  XPanel xp;
+  if (kb < ke) {
+    aw_h = apk[at];
+    aw_l = apk[kMmRows * kPanK / 8 + at];
+    load_x_panel(P.mm_kcol + kb, X, n, cb, nc, xp);
+  }
   for (int kp = kb; kp < ke; kp += kPanK) {
-    const int pj = kp - kb;  // panel start, tile-relative list position
-    __syncthreads();         // the previous panel's operands have been read
-    for (int i = threadIdx.x; i < kPanA / 4; i += blockDim.x) {  // zero both A planes
-      reinterpret_cast<uint2*>(ah)[i] = make_uint2(0u, 0u);
-      reinterpret_cast<uint2*>(al)[i] = make_uint2(0u, 0u);
-    }
-    stage_x_panel(P.mm_kcol + kp, X, n, cb, nc, bh, bl);
-    __syncthreads();
-    while (qb < bhi && __builtin_amdgcn_readfirstlane(P.mm_bpos[qb]) < pj + kPanK) ++qb;
-    for (int q = qa + wave; q < qb; q += 4) {  // one wave per block: its cells in the panel
-      const int b = __builtin_amdgcn_readfirstlane(P.tile_blk[q]);
-      const int p0 = __builtin_amdgcn_readfirstlane(P.mm_bpos[q]);
-      const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
-      const int w = P.blk[4 * b + 3] - P.blk[4 * b + 2];
-      const int ka = max(p0, pj), kz = min(p0 + w, pj + kPanK);
-      const int ra = max(br0, r0), rz = min(br1, rend);
-      if (ka >= kz || ra >= rz) continue;
-      const int nk = kz - ka, cells = (rz - ra) * nk;
-      const int w4 = (w + 3) & ~3;
-      const uint32_t* src = P.vbr_mma + P.blk_mma_ptr[b];
-      for (int e = lane; e < cells; e += 64) {
-        const int r = ra + e / nk, kk = ka + e % nk;
-        const uint32_t word = src[(i64)(r - br0) * w4 + (kk - p0)];
-        ah[(r - r0) * kPanLd + (kk - pj)] = (uint16_t)(word & 0xffffu);
-        al[(r - r0) * kPanLd + (kk - pj)] = (uint16_t)(word >> 16);
-      }
-    }
-    // blocks that end before the next panel are done
-    while (qa < qb) {
-      const int b = __builtin_amdgcn_readfirstlane(P.tile_blk[qa]);
-      if (__builtin_amdgcn_readfirstlane(P.mm_bpos[qa]) + P.blk[4 * b + 3] - P.blk[4 * b + 2] > pj + kPanK) break;
-      ++qa;
+    __syncthreads();  // the previous panel's operands have been read
+    *reinterpret_cast<uint4*>(ah + arow * kPanLd + acol) = aw_h;
+    *reinterpret_cast<uint4*>(al + arow * kPanLd + acol) = aw_l;
+    store_x_panel(xp, bh, bl);
+    if (kp + kPanK < ke) {
+      apk += 2 * kMmRows * kPanK / 8;
+      aw_h = apk[at];
+      aw_l = apk[kMmRows * kPanK / 8 + at];
+      load_x_panel(P.mm_kcol + kp + kPanK, X, n, cb, nc, xp);
     }
     __syncthreads();
 #pragma unroll

@@ -86,7 +86,7 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
     std::vector<float> t;
     std::vector<std::pair<int, int>> cand;  // (variant, far split)
     P.prm.far_split = 0;
-    for (int v : {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 13, 14}) {
+    for (int v : {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 15, 16}) {
       P.prm.spmv_variant = v;
       t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
       cand.push_back({v, 0});
@@ -98,7 +98,7 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
     }
     if (P.far.npanel) {
       P.prm.far_split = 1;
-      for (int v : {0, 1, 2, 8, 9, 10}) {
+      for (int v : {0, 1, 2, 8, 9, 10, 15, 16}) {
         P.prm.spmv_variant = v;
         t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
         cand.push_back({v, 1});
@@ -107,8 +107,8 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
     const int c = pick(t);
     P.prm.spmv_variant = cand[c].first;
     P.prm.far_split = cand[c].second;
-    std::vector<float> tp(16);
-    for (int v = 0; v <= 15; ++v) {
+    std::vector<float> tp(18);
+    for (int v = 0; v <= 17; ++v) {
       P.prm.plain_variant = v;
       tp[v] = time_ms([&] { launch_spmv_plain(P, x, y, s); }, s, reps);
     }
@@ -170,7 +170,7 @@ extern "C" sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32
     sable::set_error("NULL plan");
     return SABLE_ERR_INVALID_ARG;
   }
-  const int maxv = op == 0 ? 14 : op == 1 ? 4 : op == 2 ? 15 : op == 3 ? 1 : -1;
+  const int maxv = op == 0 ? 16 : op == 1 ? 4 : op == 2 ? 17 : op == 3 ? 1 : -1;
   if (variant < 0 || variant > maxv) {
     sable::set_error("variant %d out of range for op %d", variant, op);
     return SABLE_ERR_INVALID_ARG;

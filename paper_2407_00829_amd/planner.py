@@ -4,7 +4,8 @@ The planner replaces the search over extractor lists and delta thresholds with a
 140-128-128-15 over structure features (diagonal run-length histogram, 16x16 tile density
 histogram, row-length statistics). All numerical work runs in libsable:
   sable_features          features on the GPU
-  sable_plan_exhaustive   plans every class, times the fused SpMV, returns the fastest
+  sable_plan_exhaustive   plans every class, autotunes and times its SpMV, returns the
+                          fastest, and times plain CSR and the default list the same way
   sable_mlp_train_step    forward, softmax cross-entropy, backward and Adam on the GPU
   sable_plan_auto         features -> MLP -> plan, exhaustive fallback below tau_conf
 This module only generates matrices, stores labels (append-only JSONL, resumable), loops
@@ -38,12 +39,12 @@ def class_name(c: int) -> str:
     return f"{CLASS_LISTS[c // 3]}@{DELTAS[c % 3] / 1000:.1f}"
 
 
-def matrix_params(seed: int, nmin: float = 1e4, nmax: float = 1.5e5):
-    """Planner matrix: n ~ logU[nmin, nmax], mean row length ~ U[4, 32], proportions ~
+def matrix_params(seed: int, nmin: float = 1e4, nmax: float = 1e6):
+    """Planner matrix: n ~ logU[nmin, nmax], mean row length ~ U[4, 64], proportions ~
     Dirichlet(1,1,1) over band / block / scatter generators."""
     rng = np.random.default_rng(10_000_019 + seed)
     n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
-    rowlen = float(rng.uniform(4, 32))
+    rowlen = float(rng.uniform(4, 64))
     pi = rng.dirichlet([1.0, 1.0, 1.0])
     return n, rowlen, pi
 
@@ -70,6 +71,9 @@ def _time_ms(fn, torch, reps=10):
 
 
 def label_matrix(A, x, reps=20) -> dict:
+    """Features and the exhaustive search's class times; every time (the 15 classes, the
+    plain CSR baseline and the default list) is taken inside the library the same way: the
+    plan's kernels autotuned, then the median of three rounds of `reps` launches."""
     import torch
 
     from . import sable
@@ -77,20 +81,17 @@ def label_matrix(A, x, reps=20) -> dict:
     f = sable.sable_features(A.nrows, A.ncols, ip, ix, vv)
     xd = torch.from_numpy(x).cuda()
     y = torch.empty(A.nrows, device="cuda")
-    p, best, times = sable.sable_plan_exhaustive(A.nrows, A.ncols, ip, ix, vv, xd, y, reps)
-    t_plain = _time_ms(lambda: sable.sable_csr_spmv(p, xd, y), torch, reps)
+    p, best, times, ref = sable.sable_plan_exhaustive(A.nrows, A.ncols, ip, ix, vv, xd, y, reps,
+                                                      with_refs=True)
     p.destroy()
-    th = sable.Thresholds(delta_band_pm=750, delta_block_pm=500)
-    q = sable.sable_plan(A.nrows, A.ncols, ip, ix, vv,
-                         [sable.SABLE_X_VDIA, sable.SABLE_X_VBR, sable.SABLE_X_CSR],
-                         sable.SABLE_VBR_TILED, th)
-    t_default = _time_ms(lambda: sable.sable_spmv(q, xd, y), torch, reps)
-    q.destroy()
     return {"features": [float(v) for v in f], "times": [float(t) for t in times],
-            "best": int(best), "t_plain": t_plain, "t_default": t_default}
+            "best": int(best), "t_plain": float(ref[0]), "t_default": float(ref[1])}
 
 
-def build_labels(seeds, path: str, workers: int = 8, reps: int = 20, log=print) -> int:
+def build_labels(seeds, path: str, workers: int = 8, reps: int = 20, log=print,
+                 max_seconds: float = 0.0) -> int:
+    """Label the seeds not yet in `path` (append-only JSONL, resumable); with max_seconds > 0
+    stop after the matrix that passes that wall time."""
     done = set()
     if os.path.exists(path):
         with open(path) as fh:
@@ -103,15 +104,27 @@ def build_labels(seeds, path: str, workers: int = 8, reps: int = 20, log=print) 
     log(f"[labels] {len(done)} cached, {len(todo)} to do")
     n_new = 0
     t0 = time.time()
+    window = 2 * workers  # matrices generated ahead of the GPU (bounded host memory)
     with cf.ProcessPoolExecutor(workers) as ex, open(path, "a") as out:
-        for seed, A, x in ex.map(make_matrix, todo):
+        pending = [ex.submit(make_matrix, s) for s in todo[:window]]
+        nxt = len(pending)
+        while pending:
+            seed, A, x = pending.pop(0).result()
+            if nxt < len(todo):
+                pending.append(ex.submit(make_matrix, todo[nxt]))
+                nxt += 1
             rec = label_matrix(A, x, reps)
             rec.update(seed=int(seed), n=A.nrows, nnz=A.nnz)
             out.write(json.dumps(rec) + "\n")
             out.flush()
             n_new += 1
-            if n_new % 25 == 0:
-                log(f"[labels] {n_new}/{len(todo)} ({time.time() - t0:.0f} s)")
+            log(f"[labels] {n_new}/{len(todo)} seed {seed} n={A.nrows} nnz={A.nnz} "
+                f"best {class_name(rec['best'])} ({time.time() - t0:.0f} s)")
+            if max_seconds and time.time() - t0 > max_seconds:
+                log("[labels] time budget reached; the rest stays for the next run")
+                for f in pending:
+                    f.cancel()
+                break
     return n_new
 
 
@@ -209,13 +222,21 @@ def predict(params, mean, std, X):
     return pr.argmax(axis=1), pr.max(axis=1)
 
 
-def evaluate(params, mean, std, recs, tau_conf: float = 0.0) -> dict:
+def best_constant_class(recs) -> int:
+    """The single class with the lowest mean regret over `recs` (the planner's yardstick: one
+    fixed choice for every matrix, picked on the training records)."""
+    T = np.array([r["times"] for r in recs])
+    return int((T / T.min(axis=1, keepdims=True) - 1.0).mean(axis=0).argmin())
+
+
+def evaluate(params, mean, std, recs, tau_conf: float = 0.0, const_class: int | None = None) -> dict:
     """Regret t(pred)/t(best) - 1 over held-out records; below tau_conf the exhaustive search
     decides (regret 0 for that matrix, counted as a fallback). Gains are geomean speedups of
-    the chosen plan over the fixed default plan and over plain CSR."""
+    the chosen plan over the fixed default plan, over plain CSR and (when const_class is
+    given) over always choosing that one class."""
     X = np.array([r["features"] for r in recs], np.float32)
     pred, conf = predict(params, mean, std, X)
-    regret, g_def, g_plain, fb = [], [], [], 0
+    regret, g_def, g_plain, g_const, fb = [], [], [], [], 0
     for r, c, cf_ in zip(recs, pred, conf):
         t = np.array(r["times"])
         if cf_ < tau_conf:
@@ -224,27 +245,43 @@ def evaluate(params, mean, std, recs, tau_conf: float = 0.0) -> dict:
         regret.append(t[c] / t.min() - 1.0)
         g_def.append(r["t_default"] / t[c])
         g_plain.append(r["t_plain"] / t[c])
+        if const_class is not None:
+            g_const.append(t[const_class] / t[c])
     regret = np.array(regret)
     oracle_best = np.array([np.min(r["times"]) for r in recs])
-    return {"n": len(recs), "regret_mean": float(regret.mean()),
-            "regret_p90": float(np.percentile(regret, 90)),
-            "accuracy": float(np.mean([np.argmin(r["times"]) == c for r, c in zip(recs, pred)])),
-            "gain_vs_default_geomean": float(np.exp(np.mean(np.log(g_def)))),
-            "gain_vs_plain_csr_geomean": float(np.exp(np.mean(np.log(g_plain)))),
-            "best_vs_plain_geomean": float(np.exp(np.mean(np.log(
-                [r["t_plain"] / b for r, b in zip(recs, oracle_best)])))),
-            "fallback_rate": fb / max(1, len(recs)), "tau_conf": tau_conf}
+    geo = lambda v: float(np.exp(np.mean(np.log(v))))  # noqa: E731
+    out = {"n": len(recs), "regret_mean": float(regret.mean()),
+           "regret_p90": float(np.percentile(regret, 90)),
+           "accuracy": float(np.mean([np.argmin(r["times"]) == c for r, c in zip(recs, pred)])),
+           "gain_vs_default_geomean": geo(g_def),
+           "gain_vs_plain_csr_geomean": geo(g_plain),
+           "best_vs_plain_geomean": geo([r["t_plain"] / b for r, b in zip(recs, oracle_best)]),
+           "best_vs_default_geomean": geo([r["t_default"] / b for r, b in zip(recs, oracle_best)]),
+           "fallback_rate": fb / max(1, len(recs)), "tau_conf": tau_conf}
+    if const_class is not None:
+        T = np.array([r["times"] for r in recs])
+        cr = T[:, const_class] / T.min(axis=1) - 1.0
+        out.update(const_class=class_name(const_class), const_regret_mean=float(cr.mean()),
+                   const_regret_p90=float(np.percentile(cr, 90)),
+                   gain_vs_const_geomean=geo(g_const))
+    return out
 
 
-def save_weights(path, params, mean, std, tau=0.0):
+def save_weights(path, params, mean, std, tau=0.0, const_class=-1):
     np.savez(path, params=params.astype(np.float32), mean=mean.astype(np.float32),
-             std=std.astype(np.float32), tau=np.float32(tau))
+             std=std.astype(np.float32), tau=np.float32(tau), const_class=np.int32(const_class))
 
 
 def load_weights(path):
     z = np.load(path)
     tau = float(z["tau"]) if "tau" in z else 0.0
     return z["params"], z["mean"], z["std"], tau
+
+
+def load_const_class(path) -> int:
+    """The best single class on the training labels, stored with the weights (-1 if absent)."""
+    z = np.load(path)
+    return int(z["const_class"]) if "const_class" in z else -1
 
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "planner_weights.npz")
@@ -263,6 +300,7 @@ def main(argv=None):
     a.add_argument("--seeds", required=True)
     a.add_argument("--workers", type=int, default=8)
     a.add_argument("--reps", type=int, default=20)
+    a.add_argument("--max-seconds", type=float, default=0.0)
     b = sub.add_parser("train")
     b.add_argument("--labels", required=True)
     b.add_argument("--train", required=True)
@@ -275,10 +313,12 @@ def main(argv=None):
     c.add_argument("--test", required=True)
     c.add_argument("--weights", required=True)
     c.add_argument("--tau", type=float, default=-1.0)
+    c.add_argument("--train", default="",
+                   help="training seeds: the best constant class is chosen on them")
     args = ap.parse_args(argv)
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     if args.cmd == "label":
-        build_labels(_range(args.seeds), args.out, args.workers, args.reps, log)
+        build_labels(_range(args.seeds), args.out, args.workers, args.reps, log, args.max_seconds)
     elif args.cmd == "train":
         recs = load_labels(args.labels, set(_range(args.train)))
         val = [r for i, r in enumerate(recs) if i % 10 == 0]   # 10% validation split
@@ -287,21 +327,21 @@ def main(argv=None):
         y = robust_labels(fit, args.tol)
         params, mean, std, hist = train(X, y, epochs=args.epochs, log=log)
         tau = choose_tau(params, mean, std, val, args.target)
-        save_weights(args.out, params, mean, std, tau)
+        cc = best_constant_class(fit)
+        save_weights(args.out, params, mean, std, tau, cc)
         print(json.dumps({"trained_on": len(fit), "validation": len(val), "final_loss": hist[-1],
-                          "tau_conf": tau, "val_no_fallback": evaluate(params, mean, std, val, 0.0),
-                          "val_with_fallback": evaluate(params, mean, std, val, tau)}))
+                          "tau_conf": tau, "const_class": class_name(cc),
+                          "val_no_fallback": evaluate(params, mean, std, val, 0.0, cc),
+                          "val_with_fallback": evaluate(params, mean, std, val, tau, cc)}))
     else:
         recs = load_labels(args.labels, set(_range(args.test)))
         params, mean, std, tau = load_weights(args.weights)
         if args.tau >= 0:
             tau = args.tau
-        T = np.array([r["times"] for r in recs])
-        const = (T / T.min(axis=1, keepdims=True) - 1.0).mean(axis=0)
-        print(json.dumps({"no_fallback": evaluate(params, mean, std, recs, 0.0),
-                          "with_fallback": evaluate(params, mean, std, recs, tau),
-                          "best_constant_class": int(const.argmin()),
-                          "best_constant_regret": float(const.min())}))
+        cc = best_constant_class(load_labels(args.labels, set(_range(args.train)))
+                                 if args.train else recs)
+        print(json.dumps({"no_fallback": evaluate(params, mean, std, recs, 0.0, cc),
+                          "with_fallback": evaluate(params, mean, std, recs, tau, cc)}))
 
 
 if __name__ == "__main__":

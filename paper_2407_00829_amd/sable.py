@@ -73,7 +73,7 @@ class sable_plan_stats(ctypes.Structure):
                 ("spmv_variant", ctypes.c_int32), ("spmm_variant", ctypes.c_int32),
                 ("plain_variant", ctypes.c_int32), ("far_split", ctypes.c_int32),
                 ("far_nnz", ctypes.c_int64), ("spec_ms", ctypes.c_double),
-                ("structure_hash", ctypes.c_uint64)]
+                ("structure_hash", ctypes.c_uint64), ("partition_hash", ctypes.c_uint64)]
 
 
 class sable_partition_host(ctypes.Structure):
@@ -120,7 +120,7 @@ def lib():
         "sable_mlp_forward": [P, P, i32, P, P],
         "sable_mlp_train_step": [P, P, P, P, P, P, i32, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, i32, P, P],
-        "sable_plan_exhaustive": [P, P, P, i32, P, P, P, P],
+        "sable_plan_exhaustive": [P, P, P, i32, P, P, P, P, P],
         "sable_plan_auto": [P, P, P, P, ctypes.c_float, P, P, P, P, P, P, P],
         "sable_batch_create": [P, P, i32, P, P],
         "sable_batch_run": [P, P],
@@ -370,16 +370,21 @@ def sable_mlp_train_step(params, grads, m, v, feats, labels, lr, beta1, beta2, e
     return loss.value
 
 
-def sable_plan_exhaustive(nrows, ncols, indptr, indices, values, x, y, reps=10, stream=None):
-    """Returns (Plan, best_class, times_ms[15])."""
+def sable_plan_exhaustive(nrows, ncols, indptr, indices, values, x, y, reps=10, stream=None,
+                          with_refs=False):
+    """Returns (Plan, best_class, times_ms[15]), and with_refs the same-path times of the
+    plain CSR baseline and the default list (ref_ms[2]) as a fourth element."""
     A = csr_struct(nrows, ncols, indptr, indices, values)
     h = ctypes.c_void_p()
     bc = ctypes.c_int32()
     times = np.zeros(SABLE_NCLASS, np.float32)
+    ref = np.zeros(2, np.float32)
     _check("sable_plan_exhaustive", lib().sable_plan_exhaustive(
         ctypes.byref(A), _ptr(x), _ptr(y), int(reps), _stream(stream), ctypes.byref(h),
-        ctypes.byref(bc), times.ctypes.data_as(ctypes.c_void_p)))
-    return Plan(h, int(nrows), int(ncols), int(indices.numel())), bc.value, times
+        ctypes.byref(bc), times.ctypes.data_as(ctypes.c_void_p),
+        ref.ctypes.data_as(ctypes.c_void_p) if with_refs else None))
+    plan = Plan(h, int(nrows), int(ncols), int(indices.numel()))
+    return (plan, bc.value, times, ref) if with_refs else (plan, bc.value, times)
 
 
 def sable_plan_auto(nrows, ncols, indptr, indices, values, params, feat_mean, feat_std,

@@ -298,12 +298,12 @@ def test_every_spmv_variant_and_baseline():
     p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
     ref = oracle.spmv(A, x)
     xd = torch.from_numpy(x).cuda()
-    for v in [*range(11), 12, 13, 14]:
+    for v in [*range(11), 12, 13, 14, 15, 16]:
         sable.sable_plan_set_variant(p, 0, v)
         err = check_spmv(p, A, x)
         print(f"  variant {v}: {err:.2e}")
     y = torch.empty(A.nrows, device="cuda")
-    for v in range(16):
+    for v in range(18):
         sable.sable_plan_set_variant(p, 2, v)
         sable.sable_csr_spmv(p, xd, y)
         torch.cuda.synchronize()
@@ -322,10 +322,10 @@ def test_every_variant_on_tiny_and_ragged_shapes(shape):
     p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
     xd = torch.from_numpy(x).cuda()
     y = torch.empty(nr, device="cuda")
-    for v in [*range(11), 12, 13, 14]:
+    for v in [*range(11), 12, 13, 14, 15, 16]:
         sable.sable_plan_set_variant(p, 0, v)
         check_spmv(p, A, x)
-    for v in range(16):
+    for v in range(18):
         sable.sable_plan_set_variant(p, 2, v)
         sable.sable_csr_spmv(p, xd, y)
         torch.cuda.synchronize()
@@ -611,3 +611,29 @@ def test_structure_hash_and_autotune_cache():
     t0 = time.perf_counter()
     sable.sable_autotune(q, 0, 1, xd, y)
     assert time.perf_counter() - t0 > 5 * t_cached
+
+
+@pytest.mark.parametrize("far", [0, 1])
+def test_persistent_tiles_equal_one_tile_per_workgroup(far):
+    """The persistent streamed SpMV (variants 15, 16; plain 16, 17) runs the streamed tile body
+    on every tile in turn: its results equal the one-tile-per-workgroup launch (variants 0, 8;
+    plain 0, 10) bit for bit, with and without the far-column pass, on a matrix with many
+    more tiles than resident workgroups."""
+    A = wide_scatter(1_300_001, 1_300_001, 5)
+    x = synth.gen_dense_vector(3, A.ncols)
+    p = gpu_plan(A, [V, C], 0, oracle.Thresholds())
+    sable.sable_plan_set_variant(p, 3, far)
+    xd = torch.from_numpy(x).cuda()
+    out = {}
+    for v in (0, 15, 8, 16):
+        sable.sable_plan_set_variant(p, 0, v)
+        out[v] = run_spmv(p, A, x)
+    assert torch.equal(out[0], out[15]) and torch.equal(out[8], out[16])
+    assert oracle.rel_err(out[15].cpu().numpy(), oracle.spmv(A, x)) <= 1e-5
+    y = {}
+    for v in (0, 16, 10, 17):
+        sable.sable_plan_set_variant(p, 2, v)
+        y[v] = torch.full((A.nrows,), float("nan"), device="cuda")
+        sable.sable_csr_spmv(p, xd, y[v])
+    torch.cuda.synchronize()
+    assert torch.equal(y[0], y[16]) and torch.equal(y[10], y[17])

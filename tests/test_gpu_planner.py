@@ -112,3 +112,32 @@ def test_exhaustive_and_auto_plans():
     assert not fb2 and 0 < conf2 <= 1
     f = sable.sable_features(A.nrows, A.ncols, ip, ix, vv)
     assert c2 == int(np.argmax(pr.mlp_forward(pr.init_params(2), f[None, :])))
+
+
+def test_partition_hash_follows_the_partition():
+    """Plans of the 15 classes: equal partition hashes exactly when the exported partitions
+    (every format array, owner and slot) are equal, so the exhaustive search may time such
+    classes once."""
+    A, _ = synth.gen_mixed(5, n=12000, rowlen=10.0, pi=np.array([0.3, 0.5, 0.2]))
+    ip, ix, vv = sable.device_csr(A)
+    lists = [[3], [1, 3], [2, 3], [1, 2, 3], [2, 1, 3]]
+    seen = []
+    for li, kinds in enumerate(lists):
+        for delta in (500, 700, 900):
+            th = sable.Thresholds(delta_band_pm=delta, delta_block_pm=delta)
+            p = sable.sable_plan(A.nrows, A.ncols, ip, ix, vv, kinds, sable.SABLE_VBR_TILED, th=th)
+            h = sable.sable_plan_info(p)["partition_hash"]
+            ex = sable.sable_plan_export(p)
+            q = sable.sable_plan(A.nrows, A.ncols, ip, ix, vv, kinds, sable.SABLE_VBR_TILED, th=th)
+            assert sable.sable_plan_info(q)["partition_hash"] == h  # deterministic
+            seen.append((h, ex))
+    keys = [k for k in seen[0][1] if isinstance(seen[0][1][k], np.ndarray)]
+    distinct = 0
+    for i in range(len(seen)):
+        for j in range(i):
+            same = all(seen[i][1][k].shape == seen[j][1][k].shape and
+                       np.array_equal(seen[i][1][k].view(np.uint8), seen[j][1][k].view(np.uint8))
+                       for k in keys)
+            assert (seen[i][0] == seen[j][0]) == same, (i, j)
+            distinct += not same
+    assert distinct > 0
