@@ -102,6 +102,7 @@ def cold_tune(sable, p, op, cands, fn, reps, torch, flush):
             sable.sable_plan_set_variant(p, o, v)
         times.append(cold_launch_ms(fn, reps, torch, flush))
     best = min(times)
+    log("cold candidates: " + ", ".join(f"{c}: {t * 1e3:.1f} us" for c, t in zip(cands, times)))
     k = next(i for i, t in enumerate(times) if t <= 1.02 * best)
     for o, v in cands[k]:
         sable.sable_plan_set_variant(p, o, v)

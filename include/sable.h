@@ -200,7 +200,9 @@ sable_status sable_plan_export(sable_plan_t p, const sable_partition_host* out);
  * a gather pass over those entries (grouped by 8192-column slices of x, each staged in
  * LDS) into a product buffer owned by the plan, then the fused launch adds the products
  * in the same order as without the pass. Two calls with the same plan must therefore not
- * run concurrently on different streams. */
+ * run concurrently on different streams. A plan that is its CSR part alone (no band
+ * segment, no block) runs as sable_csr_spmv: its CSR part is the input in the input's order,
+ * and the plain kernels (the plan's plain variant) are the hybrid launch's CSR-only case. */
 sable_status sable_spmv(sable_plan_t p, const float* x, float* y, void* stream);
 
 /* Y = A X with n >= 1 right-hand sides (row-major, App. A.2). VBR blocks run on matrix
@@ -291,6 +293,8 @@ sable_status sable_autotune_cache_clear(void);
  *        with non-temporal matrix loads, 13..15 = row-length bins as SpMV 12..14, 16, 17 = 0
  *        and 10 as persistent launches (as SpMV 15, 16);
  * op 3 = far-column split of the streamed SpMV variants: 0 off, 1 on (when the plan has one).
+ * For a plan with neither bands nor blocks, op 0 selects nothing but the specialized kernel
+ * (11): its SpMV runs the plain kernels of op 2.
  * Every variant computes the same product; each is bitwise reproducible on its own. An
  * explicit SpMM variant applies to every n (it clears the per-n autotuned choices). */
 sable_status sable_plan_set_variant(sable_plan_t p, int32_t op, int32_t variant);

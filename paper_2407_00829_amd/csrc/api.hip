@@ -313,7 +313,8 @@ sable::i64 sable_plan_s::device_bytes() const {
          S->bin_off.bytes() + S->head.bytes();
   }
   b += mm_panels.kcol.bytes() + mm_panels.kptr.bytes() + mm_panels.bpos.bytes() +
-       mm_panels.apack.bytes() + mm_panels.pan_tile.bytes() + mm_panels.pan_pos.bytes();
+       mm_panels.apack.bytes() + mm_panels.amask.bytes() + mm_panels.aptr.bytes() +
+       mm_panels.pan_tile.bytes() + mm_panels.pan_pos.bytes();
   b += far.ccol.bytes() + far.far_col.bytes() + far.far_src.bytes() + far.far_val.bytes() +
        far.far_prod.bytes() + far.far_val64.bytes() + far.far_prod64.bytes() + far.chunk.bytes();
   return b;

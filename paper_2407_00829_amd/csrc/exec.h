@@ -44,7 +44,9 @@ struct PlanView {
   const int32_t* mm_kcol;
   const int32_t* mm_kptr;
   const int32_t* mm_bpos;
-  const uint16_t* mm_apack;
+  const uint4* mm_apack;
+  const uint64_t* mm_amask;
+  const i64* mm_aptr;
 };
 
 // Value arrays of the view for the executor's value type.

@@ -54,6 +54,8 @@ PlanView make_view(const sable_plan_s& P, const Schedule& S, bool plain, bool fa
     v.mm_kptr = P.mm_panels.kptr.p;
     v.mm_bpos = P.mm_panels.bpos.p;
     v.mm_apack = P.mm_panels.apack.p;
+    v.mm_amask = P.mm_panels.amask.p;
+    v.mm_aptr = P.mm_panels.aptr.p;
   }
   if (far && P.far.npanel && P.prm.far_split) {
     v.csr_col = P.far.ccol.p;
@@ -401,17 +403,23 @@ __global__ __launch_bounds__(kMmThreads, 4) void k_spmm_tile_valu(PlanView P, co
   spmm_tile(P, t * kMmRows, blockIdx.y * kMmCols, n, X, Y, ys, 0);
 }
 
-// One workgroup per panel: the tile's block cells that fall in the panel's 32 list positions,
-// as a zero-filled 64 x 32 hi plane and lo plane (built in LDS, then written out whole).
+// One workgroup per panel: the tile's block cells that fall in the panel's 32 list positions
+// are placed in a zero-filled 64 x 32 hi plane and lo plane in LDS, with the units (row, 8
+// columns) that receive a cell marked. write == 0: the panel's occupancy mask is stored;
+// write == 1: its marked units are stored in mask order from apack[2 aptr[g]] on.
 __global__ __launch_bounds__(256) void k_pack_panels(PlanView P, const int32_t* __restrict__ pan_tile,
                                                     const int32_t* __restrict__ pan_pos,
-                                                    uint16_t* __restrict__ apack) {
+                                                    uint64_t* __restrict__ amask,
+                                                    const i64* __restrict__ aptr,
+                                                    uint4* __restrict__ apack, int write) {
   __shared__ __align__(16) uint16_t pl[2 * kMmRows * kPanK];
+  __shared__ uint8_t occ[kMmRows * kPanK / 8];
   const i64 g = blockIdx.x;
   const int tile = pan_tile[g], pj = pan_pos[g];
   const int r0 = tile * kMmRows, rend = min(r0 + kMmRows, P.nrows);
   for (int i = threadIdx.x; i < 2 * kMmRows * kPanK / 4; i += blockDim.x)  // both planes
     reinterpret_cast<uint64_t*>(pl)[i] = 0ull;
+  for (int i = threadIdx.x; i < kMmRows * kPanK / 8; i += blockDim.x) occ[i] = 0;
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int q = P.tile_blk_ptr[tile] + wave; q < P.tile_blk_ptr[tile + 1]; q += 4) {
@@ -426,14 +434,28 @@ __global__ __launch_bounds__(256) void k_pack_panels(PlanView P, const int32_t* 
     for (int c = lane; c < cells; c += 64) {
       const int r = ra + c / nk, kk = ka + c % nk;
       const uint32_t word = src[(i64)(r - br0) * w4 + (kk - p0)];
-      pl[(r - r0) * kPanK + (kk - pj)] = (uint16_t)(word & 0xffffu);
-      pl[kMmRows * kPanK + (r - r0) * kPanK + (kk - pj)] = (uint16_t)(word >> 16);
+      const int e = (r - r0) * kPanK + (kk - pj);
+      pl[e] = (uint16_t)(word & 0xffffu);
+      pl[kMmRows * kPanK + e] = (uint16_t)(word >> 16);
+      occ[e >> 3] = 1;  // the same value from every writer
     }
   }
   __syncthreads();
-  uint4* out = reinterpret_cast<uint4*>(apack + g * (2 * kMmRows * kPanK));
-  for (int i = threadIdx.x; i < 2 * kMmRows * kPanK / 8; i += blockDim.x)
-    out[i] = reinterpret_cast<const uint4*>(pl)[i];
+  const int u = threadIdx.x;  // one unit per thread (256 units)
+  const bool set = occ[u] != 0;
+  const uint64_t m = __ballot(set);
+  if (!write) {
+    if (lane == 0) amask[4 * g + wave] = m;
+    return;
+  }
+  int before = 0;
+  for (int i = 0; i < wave; ++i) before += __popcll(amask[4 * g + i]);
+  if (set) {
+    const int rank = before + __popcll(m & ((1ull << lane) - 1ull));
+    uint4* out = apack + 2 * (aptr[g] + rank);
+    out[0] = reinterpret_cast<const uint4*>(pl)[u];
+    out[1] = reinterpret_cast<const uint4*>(pl + kMmRows * kPanK)[u];
+  }
 }
 
 // Blocks on matrix cores from LDS-staged panels (16x16x32 bf16 steps).
@@ -758,6 +780,12 @@ void launch_spmv(const sable_plan_s& P, const float* x, float* y, hipStream_t s)
     launch_spmv_spec(P, x, y, s);
     return;
   }
+  if (P.nseg == 0 && P.nblk == 0) {
+    // the plan is its CSR part alone, which is the input in its own order: the plain CSR
+    // kernels run it (the plain variant)
+    launch_spmv_plain(P, x, y, s);
+    return;
+  }
   if (var >= 15) {  // persistent streamed tiles (with the far-column pass when enabled)
     const PlanView v = make_view(P, P.sched[0], false, true);
     if (v.far_prod) {
@@ -879,6 +907,9 @@ void build_mm_panels(sable_plan_s& P, hipStream_t s) {
   M.kptr.reset();
   M.bpos.reset();
   M.apack.reset();
+  M.amask.reset();
+  M.aptr.reset();
+  M.nunits = 0;
   M.pan_tile.reset();
   M.pan_pos.reset();
   M.npanels = 0;
@@ -919,7 +950,27 @@ void build_mm_panels(sable_plan_s& P, hipStream_t s) {
   M.npanels = (i64)ptile.size();
   to_dev(M.pan_tile, ptile, s);
   to_dev(M.pan_pos, ppos, s);
-  M.apack.alloc((size_t)M.npanels * 2 * kMmRows * kPanK);
+  // occupancy masks first, then the unit offsets, then the units
+  M.amask.alloc((size_t)M.npanels * 4);
+  const PlanView v = make_view(P, P.sched_mm, false);
+  for (i64 g0 = 0; g0 < M.npanels; g0 += (1 << 30)) {  // grid.x limit
+    const unsigned nb = (unsigned)std::min<i64>(M.npanels - g0, 1 << 30);
+    k_pack_panels<<<nb, 256, 0, s>>>(v, M.pan_tile.p + g0, M.pan_pos.p + g0, M.amask.p + 4 * g0,
+                                     nullptr, nullptr, 0);
+    LAUNCH_CHECK();
+  }
+  std::vector<uint64_t> mask;
+  to_host(mask, M.amask.p, (size_t)M.npanels * 4, s);
+  std::vector<i64> aptr((size_t)M.npanels + 1);
+  aptr[0] = 0;
+  for (i64 g = 0; g < M.npanels; ++g) {
+    int c = 0;
+    for (int i = 0; i < 4; ++i) c += __builtin_popcountll(mask[4 * g + i]);
+    aptr[g + 1] = aptr[g] + c;
+  }
+  M.nunits = aptr[M.npanels];
+  to_dev(M.aptr, aptr, s);
+  M.apack.alloc((size_t)std::max<i64>(1, 2 * M.nunits));
   pack_mm_panels(P, s);
 }
 
@@ -929,8 +980,8 @@ void pack_mm_panels(sable_plan_s& P, hipStream_t s) {
   const PlanView v = make_view(P, P.sched_mm, false);
   for (i64 g0 = 0; g0 < M.npanels; g0 += (1 << 30)) {  // grid.x limit
     const unsigned nb = (unsigned)std::min<i64>(M.npanels - g0, 1 << 30);
-    k_pack_panels<<<nb, 256, 0, s>>>(v, M.pan_tile.p + g0, M.pan_pos.p + g0,
-                                     M.apack.p + g0 * 2 * kMmRows * kPanK);
+    k_pack_panels<<<nb, 256, 0, s>>>(v, M.pan_tile.p + g0, M.pan_pos.p + g0, M.amask.p + 4 * g0,
+                                     M.aptr.p + g0, M.apack.p, 1);
     LAUNCH_CHECK();
   }
   HIPC(hipStreamSynchronize(s));

@@ -89,14 +89,19 @@ struct MmPanels {
   DBuf<int32_t> kcol;  // tile t: kcol[kptr[t] .. kptr[t + 1])
   DBuf<int32_t> kptr;  // ntiles + 1 offsets, multiples of 32
   DBuf<int32_t> bpos;  // aligned with the schedule's tile_blk
-  // The A operand of every panel, packed at plan time from the split-bf16 words: panel g
-  // (g = kptr[t] / 32 + j for panel j of tile t) is a 64 x 32 hi plane then a 64 x 32 lo plane
-  // (bf16, row-major, zero where no block cell falls), 8 KB, so the SpMM loads it with two
-  // 16-byte loads per thread instead of gathering cells. pan_tile / pan_pos: tile and
-  // tile-relative first list position of each panel.
-  DBuf<uint16_t> apack;
+  // The A operand of every panel, packed at plan time from the split-bf16 words. Panel g
+  // (g = kptr[t] / 32 + j for panel j of tile t) is a 64 x 32 bf16 operand cut into 256 units
+  // of one row and 8 consecutive columns (unit u = 4 row + column / 8, the piece one thread
+  // loads). amask[4 g .. 4 g + 3] has bit u set when a block cell falls in unit u; the set
+  // units are stored in order from apack[2 aptr[g]] on, each as its hi then its lo 16 bytes
+  // (zero where no cell falls). A thread of the SpMM loads its unit with two 16-byte loads,
+  // or nothing when the unit is empty. pan_tile / pan_pos: tile and tile-relative first list
+  // position of each panel.
+  DBuf<uint4> apack;
+  DBuf<uint64_t> amask;
+  DBuf<i64> aptr;
   DBuf<int32_t> pan_tile, pan_pos;
-  i64 npanels = 0;
+  i64 npanels = 0, nunits = 0;
 };
 
 // What a streamed SpMV tile needs before its first dependent load, one 64-byte record per

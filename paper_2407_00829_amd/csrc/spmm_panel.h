@@ -8,7 +8,9 @@
 //         contiguous per column, the layout of the B operand of v_mfma_f32_16x16x32_bf16;
 //       * the panel's A operand, the tile's block cells that fall in it as a zero-filled
 //         64 x 32 hi plane and lo plane packed at plan time from the split-bf16 words, is
-//         copied into LDS with two 16-byte loads per thread;
+//         copied into LDS: each thread owns one unit (a row, 8 columns) and loads it with
+//         two 16-byte loads if the panel's occupancy mask says a cell falls in it (only such
+//         units are stored), else writes zeros;
 //       * both loads of the next panel are issued before this panel's products run;
 //       * each wave then runs, for its 16-column chunks and 16-row slices, three
 //         16x16x32 products hi*hi + hi*lo + lo*hi with fp32 accumulation in registers.
@@ -143,9 +145,37 @@ __device__ __forceinline__ void spmm_rows_quad(const PlanView& P, int tile, int 
                                                float* __restrict__ Y, const float* __restrict__ ys,
                                                int wave, int lane) {
   const int h = lane >> 5, cq = 4 * (lane & 31);
-  for (int rl = wave; rl < kMmRows; rl += 4) {
+  // the tile's row bounds, lane l holding the start of row r0 + l; a wave reads them with
+  // readlane (its rows are wave-uniform)
+  const int rb_lane = P.csr_ptr[min(r0 + lane, rend)];
+  const int rb_end = P.csr_ptr[rend];
+  auto row_begin = [&](int rl) { return __builtin_amdgcn_readlane(rb_lane, rl); };
+  auto row_end = [&](int rl) { return rl + 1 < rend - r0 ? __builtin_amdgcn_readlane(rb_lane, rl + 1) : rb_end; };
+  // the first 64 indices and values of the wave's next row are loaded while the current
+  // row's gathers run
+  int mc = 0;
+  float mv = 0.f;
+  if (wave < rend - r0) {
+    const int k0 = row_begin(wave), k1 = row_end(wave);
+    if (k0 < k1) {
+      const int kl = k0 + min(lane, k1 - k0 - 1);
+      mc = __builtin_nontemporal_load(P.csr_col + kl);
+      mv = __builtin_nontemporal_load(P.csr_val + kl);
+    }
+  }
+  for (int rl = wave; rl < rend - r0; rl += 4) {
     const int r = r0 + rl;
-    if (r >= rend) break;
+    const int kb = row_begin(rl), ke = row_end(rl);
+    int mc_n = 0;
+    float mv_n = 0.f;
+    if (rl + 4 < rend - r0) {
+      const int k0 = row_begin(rl + 4), k1 = row_end(rl + 4);
+      if (k0 < k1) {
+        const int kl = k0 + min(lane, k1 - k0 - 1);
+        mc_n = __builtin_nontemporal_load(P.csr_col + kl);
+        mv_n = __builtin_nontemporal_load(P.csr_val + kl);
+      }
+    }
     f32x4_t a = {0.f, 0.f, 0.f, 0.f};
     if (h == 0) {
       for (int s = P.tile_seg_lo[tile]; s < P.tile_seg_hi[tile]; ++s) {
@@ -163,34 +193,48 @@ __device__ __forceinline__ void spmm_rows_quad(const PlanView& P, int tile, int 
       a += *reinterpret_cast<const f32x4_t*>(ys + rl * kMmCols + cq);
     }
     f32x4_t cs = {0.f, 0.f, 0.f, 0.f};
-    const int ke = P.csr_ptr[r + 1];
-    for (int k = P.csr_ptr[r]; k < ke; k += 64) {
+    for (int k = kb; k < ke; k += 64) {
       const int cnt = min(64, ke - k);
-      const int kl = k + min(lane, cnt - 1);
-      const int mc = __builtin_nontemporal_load(P.csr_col + kl);
-      const float mv = __builtin_nontemporal_load(P.csr_val + kl);
+      if (k > kb) {  // rows longer than 64 entries: the next 64
+        const int kl = k + min(lane, cnt - 1);
+        mc = __builtin_nontemporal_load(P.csr_col + kl);
+        mv = __builtin_nontemporal_load(P.csr_val + kl);
+      }
       int u = 0;
-      for (; u + 8 <= cnt; u += 8) {  // four entries per half in flight
-        int cc[4];
-        float va[4];
-        f32x4_t xv[4];
+      for (; u + 16 <= cnt; u += 16) {  // eight entries per half in flight
+        int cc[8];
+        float va[8];
+        f32x4_t xv[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 8; ++j) {
           cc[j] = __shfl(mc, u + 2 * j + h);
           va[j] = __shfl(mv, u + 2 * j + h);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const f32x4_t*>(X + (i64)cc[j] * n + cb + cq);
+        for (int j = 0; j < 8; ++j) xv[j] = *reinterpret_cast<const f32x4_t*>(X + (i64)cc[j] * n + cb + cq);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cs += va[j] * xv[j];
+        for (int j = 0; j < 8; ++j) cs += va[j] * xv[j];
       }
-      for (; u < cnt; u += 2) {  // the last pairs; the odd half may have no entry
-        const int e = min(u + h, cnt - 1);
-        const int ce = __shfl(mc, e);
-        const float ve = __shfl(mv, e);
-        if (u + h < cnt) cs += ve * *reinterpret_cast<const f32x4_t*>(X + (i64)ce * n + cb + cq);
+      if (u < cnt) {  // the last 1..15 entries in one batch; lanes past the end idle
+        int cc[8];
+        float va[8];
+        f32x4_t xv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = min(u + 2 * j + h, cnt - 1);
+          cc[j] = __shfl(mc, e);
+          va[j] = __shfl(mv, e);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (u + 2 * j + h < cnt) xv[j] = *reinterpret_cast<const f32x4_t*>(X + (i64)cc[j] * n + cb + cq);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (u + 2 * j + h < cnt) cs += va[j] * xv[j];
       }
     }
+    mc = mc_n;
+    mv = mv_n;
     f32x4_t o;
     o.x = __shfl_xor(cs.x, 32);
     o.y = __shfl_xor(cs.y, 32);
@@ -250,7 +294,8 @@ __device__ __forceinline__ void store_x_panel(const XPanel& xp, uint16_t* bh, ui
 
 // Rows [r0, r0 + kMmRows) x columns [cb, cb + nc) of Y for tile `tile` of the view's 64-row
 // schedule; lds holds kPanLdsBytes.
-static_assert(kMmThreads * 8 == kMmRows * kPanK, "one 16-byte load per thread fills a 64 x 32 plane");
+static_assert(kMmThreads * 8 == kMmRows * kPanK && kMmThreads == 256,
+              "one unit of 8 bf16 per thread covers a 64 x 32 plane; four 64-bit occupancy words");
 
 __device__ __forceinline__ void spmm_tile_panel(const PlanView& P, int tile, int cb, int n,
                                                 const float* __restrict__ X, float* __restrict__ Y,
@@ -276,17 +321,34 @@ __device__ __forceinline__ void spmm_tile_panel(const PlanView& P, int tile, int
   // no panels: a plan without blocks (bands and CSR only)
   const int kb = P.mm_kptr ? __builtin_amdgcn_readfirstlane(P.mm_kptr[tile]) : 0;
   const int ke = P.mm_kptr ? __builtin_amdgcn_readfirstlane(P.mm_kptr[tile + 1]) : 0;
-  // operands of panel j: the packed A planes (two 16-byte loads per thread: row t / 4,
-  // columns 8 (t % 4) .. + 7 of each plane) and the 32 rows of X; both for the next panel load
-  // while this panel's products run
-  const uint4* apk = reinterpret_cast<const uint4*>(P.mm_apack) + (i64)(kb / kPanK) * (2 * kMmRows * kPanK / 8);
+  // operands of panel g = kp / 32: this thread's unit of A (row t / 4, columns 8 (t % 4) ..
+  // + 7; two 16-byte loads of its hi and lo words when the panel's occupancy mask has it,
+  // else zero) and the panel's 32 rows of X; both for the next panel are loaded while this
+  // panel's products run
   const int at = threadIdx.x;
   const int arow = at >> 2, acol = 8 * (at & 3);
-  uint4 aw_h = make_uint4(0u, 0u, 0u, 0u), aw_l = aw_h;
+  const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
+  uint4 aw_h = zero4, aw_l = zero4;
+  auto load_a = [&](int pg) {
+    const uint64_t* mk = P.mm_amask + 4 * (i64)pg;
+    const uint64_t m0 = mk[0], m1 = mk[1], m2 = mk[2], m3 = mk[3];
+    const uint64_t mw = wave == 0 ? m0 : wave == 1 ? m1 : wave == 2 ? m2 : m3;
+    const int before = (wave > 0 ? __popcll(m0) : 0) + (wave > 1 ? __popcll(m1) : 0) +
+                       (wave > 2 ? __popcll(m2) : 0);
+    const i64 base = P.mm_aptr[pg] + before;
+    aw_h = zero4;
+    aw_l = zero4;
+    if ((mw >> lane) & 1ull) {
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mw >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mw, 0u));
+      const uint4* src = P.mm_apack + 2 * (base + rank);
+      aw_h = src[0];
+      aw_l = src[1];
+    }
+  };
   XPanel xp;
   if (kb < ke) {
-    aw_h = apk[at];
-    aw_l = apk[kMmRows * kPanK / 8 + at];
+    load_a(kb / kPanK);
     load_x_panel(P.mm_kcol + kb, X, n, cb, nc, xp);
   }
   for (int kp = kb; kp < ke; kp += kPanK) {
@@ -295,9 +357,7 @@ __device__ __forceinline__ void spmm_tile_panel(const PlanView& P, int tile, int
     *reinterpret_cast<uint4*>(al + arow * kPanLd + acol) = aw_l;
     store_x_panel(xp, bh, bl);
     if (kp + kPanK < ke) {
-      apk += 2 * kMmRows * kPanK / 8;
-      aw_h = apk[at];
-      aw_l = apk[kMmRows * kPanK / 8 + at];
+      load_a(kp / kPanK + 1);
       load_x_panel(P.mm_kcol + kp + kPanK, X, n, cb, nc, xp);
     }
     __syncthreads();

@@ -80,39 +80,52 @@ void autotune(sable_plan_s& P, int op, int n, const float* x, float* y, hipStrea
     }
   }
   if (op == 0) {
-    // hybrid SpMV: every variant without the far-column split, then every streamed variant
-    // with it; candidates are ranked in that order, so the split is kept only where it is
-    // more than 2% faster than every variant without it
-    std::vector<float> t;
-    std::vector<std::pair<int, int>> cand;  // (variant, far split)
-    P.prm.far_split = 0;
-    for (int v : {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 15, 16}) {
-      P.prm.spmv_variant = v;
-      t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
-      cand.push_back({v, 0});
-    }
-    if (P.spec_func) {  // the run-time specialized kernel, ranked after the generic ones
-      P.prm.spmv_variant = 11;
-      t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
-      cand.push_back({11, 0});
-    }
-    if (P.far.npanel) {
-      P.prm.far_split = 1;
-      for (int v : {0, 1, 2, 8, 9, 10, 15, 16}) {
-        P.prm.spmv_variant = v;
-        t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
-        cand.push_back({v, 1});
-      }
-    }
-    const int c = pick(t);
-    P.prm.spmv_variant = cand[c].first;
-    P.prm.far_split = cand[c].second;
     std::vector<float> tp(18);
     for (int v = 0; v <= 17; ++v) {
       P.prm.plain_variant = v;
       tp[v] = time_ms([&] { launch_spmv_plain(P, x, y, s); }, s, reps);
     }
     P.prm.plain_variant = pick(tp);
+    if (P.nseg == 0 && P.nblk == 0) {
+      // a CSR-only plan runs its SpMV through the plain kernels (the variant just chosen);
+      // only a run-time specialized kernel competes with them
+      P.prm.far_split = 0;
+      P.prm.spmv_variant = 0;
+      if (P.spec_func) {
+        const float tb = tp[P.prm.plain_variant];
+        P.prm.spmv_variant = 11;
+        const float t11 = time_ms([&] { launch_spmv(P, x, y, s); }, s, reps);
+        if (!(t11 < tb / 1.02f)) P.prm.spmv_variant = 0;
+      }
+    } else {
+      // hybrid SpMV: every variant without the far-column split, then every streamed variant
+      // with it; candidates are ranked in that order, so the split is kept only where it is
+      // more than 2% faster than every variant without it
+      std::vector<float> t;
+      std::vector<std::pair<int, int>> cand;  // (variant, far split)
+      P.prm.far_split = 0;
+      for (int v : {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 15, 16}) {
+        P.prm.spmv_variant = v;
+        t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
+        cand.push_back({v, 0});
+      }
+      if (P.spec_func) {  // the run-time specialized kernel, ranked after the generic ones
+        P.prm.spmv_variant = 11;
+        t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
+        cand.push_back({11, 0});
+      }
+      if (P.far.npanel) {
+        P.prm.far_split = 1;
+        for (int v : {0, 1, 2, 8, 9, 10, 15, 16}) {
+          P.prm.spmv_variant = v;
+          t.push_back(time_ms([&] { launch_spmv(P, x, y, s); }, s, reps));
+          cand.push_back({v, 1});
+        }
+      }
+      const int c = pick(t);
+      P.prm.spmv_variant = cand[c].first;
+      P.prm.far_split = cand[c].second;
+    }
   } else {
     // x / y hold X (ncols x n) and Y (nrows x n); the choice is kept per n
     std::vector<float> t(5);

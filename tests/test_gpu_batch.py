@@ -44,18 +44,22 @@ STREAMED = (0, 1, 2, 8, 9, 10)
 def standalone(plans, items):
     """Standalone results with the kernels a batch runs: SpMV items with the plan's streamed
     tile variant (the 256-row streamed tile, variant 0, for any other variant) without the
-    far-column pass, SpMM items as planned."""
+    far-column pass, SpMM items as planned. A CSR-only plan's SpMV runs the plain kernels, so
+    its streamed tile is the plain variant of the same tile height."""
     outs = []
     for p, (op, n, x, y) in zip(plans, items):
         z = torch.empty_like(y)
         if op == 0:
             info = sable.sable_plan_info(p)
-            v, fs = info["spmv_variant"], info["far_split"]
-            sable.sable_plan_set_variant(p, 0, v if v in STREAMED else 0)
+            v, fs, pv = info["spmv_variant"], info["far_split"], info["plain_variant"]
+            vs = v if v in STREAMED else 0
+            sable.sable_plan_set_variant(p, 0, vs)
             sable.sable_plan_set_variant(p, 3, 0)
+            sable.sable_plan_set_variant(p, 2, vs if vs < 8 else vs + 2)
             sable.sable_spmv(p, x, z)
             sable.sable_plan_set_variant(p, 0, v)
             sable.sable_plan_set_variant(p, 3, fs)
+            sable.sable_plan_set_variant(p, 2, pv)
         else:
             sable.sable_spmm(p, x, z, n)
         outs.append(z)
