@@ -625,7 +625,8 @@ def run_spmm(args, torch, sable, synth):
         "rocsparse_csrmm": None if rs_ms is None else {
             "launch_ms": round(rs_ms, 4), "gflops": round(2.0 * A.nnz * n / (rs_ms * 1e-3) / 1e9, 2),
             "rel_err_fp64_sampled": rs_err, "speedup_hybrid_vs_rocsparse": round(rs_ms / ev_ms, 4)},
-        "partition": {k: info[k] for k in ("nseg", "vdia_nnz", "nblk", "vbr_nnz", "csr_nnz")},
+        "partition": {k: info[k] for k in ("nseg", "vdia_nnz", "nblk", "vbr_nnz", "csr_nnz",
+                                           "mm_panels", "mm_units")},
         "spmm_mode": info["spmm_variant"],
         "plan_ms": round(info["plan_ms"], 1),
     }

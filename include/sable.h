@@ -138,6 +138,8 @@ typedef struct {
                               entry and the VDIA segments and VBR blocks. Equal hashes mean
                               the same formats with the same layout, whatever the extractor
                               list or thresholds that produced them */
+  int64_t mm_panels;       /* SpMM operand panels (64 rows x 32 block columns) */
+  int64_t mm_units;        /* their occupied units (one row x 8 columns, 32 bytes each) */
 } sable_plan_stats;
 
 /* Host buffers for sable_plan_export, sized from sable_plan_info:

@@ -426,6 +426,8 @@ sable_status sable_plan_info(sable_plan_t p, sable_plan_stats* o) {
     o->device_bytes = p->device_bytes();
     o->structure_hash = p->structure_hash;
     o->partition_hash = p->partition_hash;
+    o->mm_panels = p->mm_panels.npanels;
+    o->mm_units = p->mm_panels.nunits;
     o->plan_ms = p->plan_ms;
     o->spmv_variant = p->prm.spmv_variant;
     o->spmm_variant = p->prm.spmm_mode;

@@ -459,7 +459,7 @@ __global__ __launch_bounds__(256) void k_pack_panels(PlanView P, const int32_t* 
 }
 
 // Blocks on matrix cores from LDS-staged panels (16x16x32 bf16 steps).
-__global__ __launch_bounds__(kMmThreads, 4) void k_spmm_panel(PlanView P, const float* __restrict__ X,
+__global__ __launch_bounds__(kMmThreads, 5) void k_spmm_panel(PlanView P, const float* __restrict__ X,
                                                           float* __restrict__ Y, int n) {
   __shared__ __align__(16) uint8_t lds[kPanLdsBytes];
   const int ntile = (P.nrows + kMmRows - 1) / kMmRows;

@@ -255,13 +255,12 @@ struct XPanel {
   float v[4][4];  // [k][column]
 };
 
-__device__ __forceinline__ void load_x_panel(const int32_t* __restrict__ kcol, const float* __restrict__ X,
+// Thread t loads panel rows 4 (t % 8) .. + 3 (X rows row[0..3], -1 for padding) at columns
+// cb + 4 (t / 8) .. + 3.
+__device__ __forceinline__ void load_x_panel(const int (&row)[4], const float* __restrict__ X,
                                              int n, int cb, int nc, XPanel& xp) {
   const int t = threadIdx.x;
-  const int k0 = 4 * (t & 7), c0 = 4 * (t >> 3);
-  int row[4];
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk) row[kk] = kcol[k0 + kk];
+  const int c0 = 4 * (t >> 3);
   if ((n & 3) == 0 && c0 + 4 <= nc) {
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -321,35 +320,51 @@ __device__ __forceinline__ void spmm_tile_panel(const PlanView& P, int tile, int
   // no panels: a plan without blocks (bands and CSR only)
   const int kb = P.mm_kptr ? __builtin_amdgcn_readfirstlane(P.mm_kptr[tile]) : 0;
   const int ke = P.mm_kptr ? __builtin_amdgcn_readfirstlane(P.mm_kptr[tile + 1]) : 0;
-  // operands of panel g = kp / 32: this thread's unit of A (row t / 4, columns 8 (t % 4) ..
-  // + 7; two 16-byte loads of its hi and lo words when the panel's occupancy mask has it,
-  // else zero) and the panel's 32 rows of X; both for the next panel are loaded while this
-  // panel's products run
+  // Panel g = kp / 32 goes through three stages, one panel apart: its indices (this thread's
+  // four X row numbers, the occupancy mask and the first unit of A), then its data (this
+  // thread's unit of A: row t / 4, columns 8 (t % 4) .. + 7, two 16-byte loads of hi and lo
+  // words when the mask has it, else zero; and its 4 x 4 piece of the 32 rows of X), then its
+  // products from LDS. While panel g's products run, the data of g + 1 and the indices of
+  // g + 2 are in flight, so a panel waits for one round trip at most.
   const int at = threadIdx.x;
   const int arow = at >> 2, acol = 8 * (at & 3);
+  const int xk0 = 4 * (at & 7);
   const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
-  uint4 aw_h = zero4, aw_l = zero4;
-  auto load_a = [&](int pg) {
+  struct PanIdx {
+    int row[4];
+    uint64_t m0, m1, m2, m3;
+    i64 base;
+  };
+  auto load_idx = [&](int pg, PanIdx& q) {
+    const int4 r4 = *reinterpret_cast<const int4*>(P.mm_kcol + (i64)pg * kPanK + xk0);
+    q.row[0] = r4.x; q.row[1] = r4.y; q.row[2] = r4.z; q.row[3] = r4.w;
     const uint64_t* mk = P.mm_amask + 4 * (i64)pg;
-    const uint64_t m0 = mk[0], m1 = mk[1], m2 = mk[2], m3 = mk[3];
-    const uint64_t mw = wave == 0 ? m0 : wave == 1 ? m1 : wave == 2 ? m2 : m3;
-    const int before = (wave > 0 ? __popcll(m0) : 0) + (wave > 1 ? __popcll(m1) : 0) +
-                       (wave > 2 ? __popcll(m2) : 0);
-    const i64 base = P.mm_aptr[pg] + before;
+    q.m0 = mk[0]; q.m1 = mk[1]; q.m2 = mk[2]; q.m3 = mk[3];
+    q.base = P.mm_aptr[pg];
+  };
+  uint4 aw_h = zero4, aw_l = zero4;
+  XPanel xp;
+  auto load_data = [&](const PanIdx& q) {
+    const uint64_t mw = wave == 0 ? q.m0 : wave == 1 ? q.m1 : wave == 2 ? q.m2 : q.m3;
+    const int before = (wave > 0 ? __popcll(q.m0) : 0) + (wave > 1 ? __popcll(q.m1) : 0) +
+                       (wave > 2 ? __popcll(q.m2) : 0);
     aw_h = zero4;
     aw_l = zero4;
     if ((mw >> lane) & 1ull) {
       const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mw >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mw, 0u));
-      const uint4* src = P.mm_apack + 2 * (base + rank);
+      const uint4* src = P.mm_apack + 2 * (q.base + before + rank);
       aw_h = src[0];
       aw_l = src[1];
     }
+    load_x_panel(q.row, X, n, cb, nc, xp);
   };
-  XPanel xp;
+  PanIdx qn;  // indices of the panel after the one whose data is in flight
   if (kb < ke) {
-    load_a(kb / kPanK);
-    load_x_panel(P.mm_kcol + kb, X, n, cb, nc, xp);
+    PanIdx q0;
+    load_idx(kb / kPanK, q0);
+    if (kb + kPanK < ke) load_idx(kb / kPanK + 1, qn);
+    load_data(q0);
   }
   for (int kp = kb; kp < ke; kp += kPanK) {
     __syncthreads();  // the previous panel's operands have been read
@@ -357,8 +372,9 @@ __device__ __forceinline__ void spmm_tile_panel(const PlanView& P, int tile, int
     *reinterpret_cast<uint4*>(al + arow * kPanLd + acol) = aw_l;
     store_x_panel(xp, bh, bl);
     if (kp + kPanK < ke) {
-      load_a(kp / kPanK + 1);
-      load_x_panel(P.mm_kcol + kp + kPanK, X, n, cb, nc, xp);
+      const PanIdx q = qn;
+      if (kp + 2 * kPanK < ke) load_idx(kp / kPanK + 2, qn);
+      load_data(q);
     }
     __syncthreads();
 #pragma unroll

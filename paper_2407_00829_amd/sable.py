@@ -73,7 +73,8 @@ class sable_plan_stats(ctypes.Structure):
                 ("spmv_variant", ctypes.c_int32), ("spmm_variant", ctypes.c_int32),
                 ("plain_variant", ctypes.c_int32), ("far_split", ctypes.c_int32),
                 ("far_nnz", ctypes.c_int64), ("spec_ms", ctypes.c_double),
-                ("structure_hash", ctypes.c_uint64), ("partition_hash", ctypes.c_uint64)]
+                ("structure_hash", ctypes.c_uint64), ("partition_hash", ctypes.c_uint64),
+                ("mm_panels", ctypes.c_int64), ("mm_units", ctypes.c_int64)]
 
 
 class sable_partition_host(ctypes.Structure):

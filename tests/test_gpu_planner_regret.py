@@ -1,6 +1,11 @@
 """Live regret of the trained planner (paper_2407_00829_amd/planner_weights.npz) on held-out
-matrices: the exhaustive timed search is the yardstick; the learned choice must stay close to it
-and beat the fixed default plan on average."""
+matrices of the planner's generator (n ~ logU[1e4, 1e6], mean row length ~ U[4, 64]): each
+matrix is labelled afresh by the exhaustive timed search (every class, the plain CSR kernel and
+the default list timed the same way inside the library). The shipped policy (the network's
+class, the exhaustive search below the stored confidence threshold) must stay within 5% of the
+fastest class on average; the network alone must do at least as well as always choosing the
+best single class (stored with the weights, chosen on the training labels), and the shipped
+choice must beat the paper's default list."""
 import numpy as np
 import pytest
 
@@ -13,25 +18,39 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 from paper_2407_00829_amd import sable  # noqa: E402
 
+SEEDS = range(100000, 100032)
+
 
 def test_learned_plan_regret_and_gain():
     params, mean, std, tau = planner.load_weights(planner.WEIGHTS)
+    cc = planner.load_const_class(planner.WEIGHTS)
+    assert 0 <= cc < planner.NCLASS
     P = torch.from_numpy(params).cuda()
-    regrets, gains = [], []
-    for seed in range(100000, 100016):
+    r_net, r_ship, r_const, g_def, g_plain, fb_count = [], [], [], [], [], 0
+    for seed in SEEDS:
         _, A, x = planner.make_matrix(seed)
         rec = planner.label_matrix(A, x, reps=20)
         ip, ix, vv = sable.device_csr(A)
         xd = torch.from_numpy(x).cuda()
         y = torch.empty(A.nrows, device="cuda")
         p, c, conf, fb = sable.sable_plan_auto(A.nrows, A.ncols, ip, ix, vv, P, mean, std, 0.0, xd, y)
-        assert not fb and 0 <= c < 15
+        p.destroy()
+        assert not fb and 0 <= c < planner.NCLASS and 0.0 < conf <= 1.0
         t = np.array(rec["times"])
-        regrets.append(t[c] / t.min() - 1.0)
-        gains.append(rec["t_default"] / t[c])
-        print(f"  seed {seed}: class {planner.class_name(c)} regret {regrets[-1]:.3f}")
-    mean_regret = float(np.mean(regrets))
-    gain = float(np.exp(np.mean(np.log(gains))))
-    print(f"  mean regret {mean_regret:.4f}, geomean gain over the default plan {gain:.3f}")
-    assert mean_regret <= 0.15
-    assert gain >= 1.0
+        best = int(np.argmin(t))
+        shipped = best if conf < tau else c  # below tau the exhaustive search decides
+        fb_count += conf < tau
+        r_net.append(t[c] / t.min() - 1.0)
+        r_ship.append(t[shipped] / t.min() - 1.0)
+        r_const.append(t[cc] / t.min() - 1.0)
+        g_def.append(rec["t_default"] / t[shipped])
+        g_plain.append(rec["t_plain"] / t[shipped])
+        print(f"  seed {seed} n={A.nrows}: net {planner.class_name(c)} ({conf:.2f}) regret "
+              f"{r_net[-1]:.3f}, shipped {r_ship[-1]:.3f}, {planner.class_name(cc)} {r_const[-1]:.3f}")
+    geo = lambda v: float(np.exp(np.mean(np.log(v))))  # noqa: E731
+    print(f"  mean regret: shipped {np.mean(r_ship):.4f} (fallback {fb_count}/{len(r_net)}), "
+          f"network {np.mean(r_net):.4f}, best single class {np.mean(r_const):.4f}; "
+          f"geomean gain over the default list {geo(g_def):.3f}, over plain CSR {geo(g_plain):.3f}")
+    assert np.mean(r_ship) <= 0.05
+    assert np.mean(r_net) <= np.mean(r_const)
+    assert geo(g_def) >= 1.0
