@@ -65,17 +65,22 @@ def _dispatch_order(r):
     return 0
 
 
-def counter_mean_kib(d, kernel, last=0):
+def counter_mean_kib(d, kernel, last=0, drop_last=0, first=0):
     """Mean counter value per dispatch; kernel may name several kernels joined by ' + '
     (one product launching each once), whose means are added. last > 0: only the last
-    `last` dispatches of each kernel (in dispatch order)."""
+    `last` dispatches of each kernel (in dispatch order); drop_last > 0: all but the last
+    `drop_last`; first > 0: the first `first`."""
     total, count = 0.0, None
     rows = _csv(d, "counter_collection.csv")
     for k in kernel.split(" + "):
         sel = sorted((r for r in rows if k in r["Kernel_Name"]), key=_dispatch_order)
         vals = [float(r["Counter_Value"]) for r in sel]
-        if last:
+        if first:
+            vals = vals[:first]
+        elif last:
             vals = vals[-last:]
+        elif drop_last:
+            vals = vals[:-drop_last]
         if not vals:
             raise ValueError(f"kernel {k!r} not found under {d}")
         total += sum(vals) / len(vals)
@@ -116,6 +121,13 @@ def pmc_summary(argv):
     ap.add_argument("--useful-flop", type=float, default=0.0,
                     help="algorithmic FLOP of one dispatch (2 nnz n x 3 products)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    ap.add_argument("--last", type=int, default=0,
+                    help="only the last N dispatches of the kernel (the cache-cold launches)")
+    ap.add_argument("--drop-last", type=int, default=0,
+                    help="all but the last N dispatches of the kernel (the warm launches)")
+    ap.add_argument("--first", type=int, default=0,
+                    help="only the first N dispatches of the kernel (the benchmark's own plan)")
+    ap.add_argument("--note", default="", help="a line describing which launches were counted")
     a = ap.parse_args(argv)
     by, passes = {}, []
     for d in a.dir:
@@ -124,22 +136,44 @@ def pmc_summary(argv):
             raise ValueError(f"kernel {a.kernel!r} not found under {d}")
         names = sorted({r["Counter_Name"] for r in rows})
         passes.append(names)
-        for r in rows:
-            by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for name in names:
+            vals = [float(r["Counter_Value"]) for r in
+                    sorted((r for r in rows if r["Counter_Name"] == name), key=_dispatch_order)]
+            if a.first:
+                vals = vals[:a.first]
+            elif a.last:
+                vals = vals[-a.last:]
+            elif a.drop_last:
+                vals = vals[:-a.drop_last]
+            by.setdefault(name, []).extend(vals)
     mean = {k: sum(v) / len(v) for k, v in by.items()}
     st = [r for r in kernel_stats(a.trace) if a.kernel in r["Name"]]
     avg_us = float(st[0]["AverageNs"]) / 1e3 if st else 0.0
+    sel_us, sel_what = avg_us, ""
+    if st and (a.first or a.last or a.drop_last):  # durations of the counted dispatches only
+        n_all = int(st[0]["Calls"])
+        if a.first:
+            sel_us, sel_what = timed_mean_us(a.trace, a.kernel, 0, a.first), f"the first {a.first}"
+        elif a.last:
+            sel_us, sel_what = last_mean_us(a.trace, a.kernel, a.last), f"the last {a.last}"
+        else:
+            sel_us = timed_mean_us(a.trace, a.kernel, 0, n_all - a.drop_last)
+            sel_what = f"those before the last {a.drop_last}"
+        avg_us = sel_us
     md = [f"# {a.name}: rocprofv3 counters of `{a.kernel}`", "",
           "Commands (run from /tmp with TMPDIR=/tmp; DIR is an output directory):", "",
           *[f"    rocprofv3 --pmc {' '.join(p)} --output-format csv -d DIR -o run -- {a.cmd}"
             for p in passes],
           f"    rocprofv3 --kernel-trace --stats --output-format csv -d DIR -o run -- {a.trace_cmd}", "",
+          *([a.note, ""] if a.note else []),
           "| counter | mean per dispatch |", "|---|---|"]
     for k in sorted(mean):
         md.append(f"| {k} | {mean[k]:.6g} |")
     md.append("")
     if st:
-        md.append(f"* Kernel-trace average duration: {avg_us:.1f} us over {st[0]['Calls']} dispatches.")
+        md.append(f"* Kernel-trace average duration: {float(st[0]['AverageNs']) / 1e3:.1f} us over "
+                  f"{st[0]['Calls']} dispatches" + (f"; {sel_us:.1f} us over the counted ones "
+                                                    f"({sel_what})." if sel_what else "."))
     if "SQ_WAIT_ANY" in mean and "SQ_WAVE_CYCLES" in mean:
         md.append(f"* Waves waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES): "
                   f"{100 * mean['SQ_WAIT_ANY'] / mean['SQ_WAVE_CYCLES']:.1f}% of their cycles.")
@@ -162,7 +196,7 @@ def pmc_summary(argv):
         if a.useful_flop:
             md.append(f"* Algorithmic split-bf16 work {a.useful_flop / 1e9:.1f} GFLOP: "
                       f"{100 * a.useful_flop / fl:.1f}% of the issued MFMA work is useful "
-                      "(the rest is zero padding of the blocks to 16x16x16 steps).")
+                      "(the rest multiplies the zero fill of the operand tiles).")
     os.makedirs(a.out, exist_ok=True)
     with open(os.path.join(a.out, f"{a.name}.md"), "w") as f:
         f.write("\n".join(md) + "\n")
@@ -238,11 +272,17 @@ def main(argv=None):
     ap.add_argument("--last", type=int, default=0,
                     help="counters and durations of the last N dispatches of the kernel only "
                          "(the benchmark's final cache-cold launches)")
+    ap.add_argument("--drop-last", type=int, default=0,
+                    help="counters of all but the last N dispatches of the kernel (the warm "
+                         "launches before the cache-cold ones)")
+    ap.add_argument("--first", type=int, default=0,
+                    help="counters and durations of the first N dispatches of the kernel only "
+                         "(the benchmark's own plan, before any baseline plan)")
     a = ap.parse_args(argv)
     rows = kernel_stats(a.trace)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    f_k, nf = counter_mean_kib(a.fetch, a.kernel, a.last)
-    w_k, nw = counter_mean_kib(a.write, a.kernel, a.last)
+    f_k, nf = counter_mean_kib(a.fetch, a.kernel, a.last, a.drop_last, a.first)
+    w_k, nw = counter_mean_kib(a.write, a.kernel, a.last, a.drop_last, a.first)
     fc, _ = counter_mean_kib(a.fetch_copy, a.copy_kernel)
     wc, _ = counter_mean_kib(a.write_copy, a.copy_kernel)
     half = a.copy_bytes / 2  # the copy reads half and writes half of copy_bytes
@@ -264,7 +304,9 @@ def main(argv=None):
     for r in rows[:12]:
         md.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
-    md += ["", f"## HBM bytes of `{a.kernel}`" + (f" (last {a.last} dispatches)" if a.last else ""), "",
+    md += ["", f"## HBM bytes of `{a.kernel}`" + (f" (last {a.last} dispatches)" if a.last else "")
+           + (f" (all but the last {a.drop_last} dispatches)" if a.drop_last else "")
+           + (f" (first {a.first} dispatches)" if a.first else ""), "",
            f"* FETCH_SIZE mean {f_k:.1f} KiB per dispatch over {nf} dispatches; WRITE_SIZE "
            f"{w_k:.1f} KiB over {nw}.",
            f"* Calibration with a plain device copy of {a.copy_bytes / 2 ** 30:.2f} GiB "
@@ -285,6 +327,10 @@ def main(argv=None):
             tm = timed_mean_us(a.trace, a.kernel, first, count)
             md.append(f"* Timed region (dispatches {first}..{first + count - 1} of the kernel, "
                       f"after the warm-up and before the cache-cold launches): mean {tm:.2f} us -> "
+                      f"{(fetch_b + write_b) / (tm * 1e-6) / 1e12:.2f} TB/s of counted traffic.")
+        if a.first:
+            tm = timed_mean_us(a.trace, a.kernel, 0, a.first)
+            md.append(f"* First {a.first} dispatches of the kernel: mean {tm:.2f} us -> "
                       f"{(fetch_b + write_b) / (tm * 1e-6) / 1e12:.2f} TB/s of counted traffic.")
         if a.last:
             tm = last_mean_us(a.trace, a.kernel, a.last)
