@@ -133,13 +133,22 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {  // splitmix64 finaliser
   return z ^ (z >> 31);
 }
 
+// A wave's 64 partial sums added (mod 2^64) and added once to *out.
+__device__ __forceinline__ void add_wave_sum(uint64_t acc, unsigned long long* out) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += (uint64_t)__shfl_xor((unsigned long long)acc, o);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, (unsigned long long)acc);
+}
+
+constexpr unsigned kHashBlocks = 2048;  // grid-stride: a few thousand atomics per hash
+
 // sum over k of mix(k, a[k]) mod 2^64 (order-independent, so the atomic sum is exact)
 __global__ void k_hash_i32(const int32_t* __restrict__ a, i64 n, uint64_t salt,
                            unsigned long long* __restrict__ out) {
   uint64_t acc = 0;
   for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x)
     acc += mix64(((uint64_t)k << 32) ^ (uint32_t)a[k] ^ salt);
-  atomicAdd(out, (unsigned long long)acc);
+  add_wave_sum(acc, out);
 }
 
 uint64_t mix64_host(uint64_t z) {
@@ -155,10 +164,10 @@ uint64_t structure_hash(const sable_csr& A, const sable_extractor* list, int nli
                         const sable_thresholds& th, hipStream_t s) {
   DBuf<unsigned long long> d(2);
   HIPC(hipMemsetAsync(d.p, 0, 2 * sizeof(unsigned long long), s));
-  k_hash_i32<<<grid_for((i64)A.nrows + 1, 256), 256, 0, s>>>(A.indptr, (i64)A.nrows + 1, 0x9e3779b97f4a7c15ull, d.p);
+  k_hash_i32<<<grid_for((i64)A.nrows + 1, 256, kHashBlocks), 256, 0, s>>>(A.indptr, (i64)A.nrows + 1, 0x9e3779b97f4a7c15ull, d.p);
   LAUNCH_CHECK();
   if (A.nnz) {
-    k_hash_i32<<<grid_for(A.nnz, 256), 256, 0, s>>>(A.indices, A.nnz, 0x7f4a7c159e3779b9ull, d.p + 1);
+    k_hash_i32<<<grid_for(A.nnz, 256, kHashBlocks), 256, 0, s>>>(A.indices, A.nnz, 0x7f4a7c159e3779b9ull, d.p + 1);
     LAUNCH_CHECK();
   }
   unsigned long long h2[2];
@@ -181,7 +190,7 @@ __global__ void k_hash_owner_slot(const int8_t* __restrict__ owner, const i64* _
   uint64_t acc = 0;
   for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x)
     acc += mix64(((uint64_t)k << 8 | (uint8_t)owner[k]) ^ mix64((uint64_t)slot[k] + 0x2545f4914f6cdd1dull));
-  atomicAdd(out, (unsigned long long)acc);
+  add_wave_sum(acc, out);
 }
 
 // Hash of the partition a plan built: which format holds each entry and where, plus the
@@ -192,11 +201,11 @@ uint64_t partition_hash(const sable_plan_s& P, hipStream_t s) {
   HIPC(hipMemsetAsync(d.p, 0, 6 * sizeof(unsigned long long), s));
   auto h32 = [&](const int32_t* a, i64 n, uint64_t salt, int k) {
     if (n <= 0) return;
-    k_hash_i32<<<grid_for(n, 256), 256, 0, s>>>(a, n, salt, d.p + k);
+    k_hash_i32<<<grid_for(n, 256, kHashBlocks), 256, 0, s>>>(a, n, salt, d.p + k);
     LAUNCH_CHECK();
   };
   if (P.nnz) {
-    k_hash_owner_slot<<<grid_for(P.nnz, 256), 256, 0, s>>>(P.owner.p, P.slot.p, P.nnz, d.p);
+    k_hash_owner_slot<<<grid_for(P.nnz, 256, kHashBlocks), 256, 0, s>>>(P.owner.p, P.slot.p, P.nnz, d.p);
     LAUNCH_CHECK();
   }
   h32(P.blk.p, 4 * (i64)P.nblk, 0x3c6ef372fe94f82bull, 1);

@@ -415,8 +415,18 @@ __device__ __forceinline__ void stream_body(const PlanView& P, StreamTile<RPT, T
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
+      // the row's products in index order; eight LDS reads are issued before their adds, so
+      // a long row costs one LDS round trip per eight entries instead of one per entry
       const int a = max(kb[q], e0), b = min(ke[q], e0 + n);
-      for (int k = a; k < b; ++k) cs[q] += prod[k - e0];
+      int k = a;
+      for (; k + 8 <= b; k += 8) {
+        T v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = prod[k - e0 + i];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cs[q] += v[i];
+      }
+      for (; k < b; ++k) cs[q] += prod[k - e0];
     }
   }
 #pragma unroll

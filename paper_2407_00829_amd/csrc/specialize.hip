@@ -104,7 +104,15 @@ std::string spec_source(const sable_plan_s& P, const std::vector<int32_t>& srs,
        "    for (int u = 0; u < 8; ++u) prod[t + " << kSpecRows << " * u] = e0 + t + " << kSpecRows << " * u < ee ? aa[u] * vv[u] : 0.f;\n"
        "    __syncthreads();\n"
        "    const int a = max(kb, e0), b = min(ke, e0 + " << 8 * kSpecRows << ");\n"
-       "    for (int k = a; k < b; ++k) cs += prod[k - e0];\n"
+       "    int k = a;\n"
+       "    for (; k + 8 <= b; k += 8) {\n"
+       "      float v[8];\n"
+       "#pragma unroll\n"
+       "      for (int i = 0; i < 8; ++i) v[i] = prod[k - e0 + i];\n"
+       "#pragma unroll\n"
+       "      for (int i = 0; i < 8; ++i) cs += v[i];\n"
+       "    }\n"
+       "    for (; k < b; ++k) cs += prod[k - e0];\n"
        "  }\n"
        "  if (act) y[r] = acc + cs;\n"
        "}\n";
