@@ -349,6 +349,48 @@ def test_spmm_modes_and_widths(n):
         check_spmm(p, A, n, seed=n)
 
 
+def test_spmm_panel_unit_counts():
+    """The SpMM operand panels store only occupied units (one row x 8 columns): every block cell
+    falls in exactly one unit and a panel has 256 units, so 8 units >= cells and units <= 256
+    panels; a plan without blocks has no panels."""
+    A, _ = synth.gen_c1(4, n=1536)
+    th = oracle.Thresholds(amin_band=256, amin_block=256)
+    p = gpu_plan(A, [V, B, C], oracle.MODE_TILED, th)
+    st = sable.sable_plan_info(p)
+    assert st["nblk"] > 0 and st["mm_panels"] > 0
+    assert 8 * st["mm_units"] >= st["vbr_cells"] and st["mm_units"] <= 256 * st["mm_panels"]
+    q = gpu_plan(A, [V, C], oracle.MODE_TILED, th)
+    sq = sable.sable_plan_info(q)
+    assert sq["nblk"] == 0 and sq["mm_panels"] == 0 and sq["mm_units"] == 0
+    check_spmm(q, A, 128, seed=3)
+
+
+def test_csr_only_plan_runs_the_plain_kernels():
+    """A plan whose partition is CSR alone runs its SpMV through the plain CSR kernels: after
+    autotuning, sable_spmv equals sable_csr_spmv bit for bit, for a [CSR] plan and for a
+    [VDIA, VBR, CSR] plan whose extractors find nothing."""
+    A = synth.gen_random_small(11, 3000, 2500, 0.004)
+    x = synth.gen_dense_vector(4, A.ncols)
+    xd = torch.from_numpy(x).cuda()
+    for kinds in ([C], [V, B, C]):
+        p = gpu_plan(A, kinds, oracle.MODE_TILED, oracle.Thresholds())
+        st = sable.sable_plan_info(p)
+        assert st["nseg"] == 0 and st["nblk"] == 0
+        y1 = torch.full((A.nrows,), float("nan"), device="cuda")
+        y2 = torch.full((A.nrows,), float("nan"), device="cuda")
+        sable.sable_autotune(p, 0, 1, xd, y1)
+        sable.sable_spmv(p, xd, y1)
+        sable.sable_csr_spmv(p, xd, y2)
+        torch.cuda.synchronize()
+        assert torch.equal(y1.view(torch.int32), y2.view(torch.int32))
+        assert oracle.rel_err(y1.cpu().numpy(), oracle.spmv(A, x)) <= 1e-5
+        for v in (0, 3, 8, 12, 15):  # every hybrid variant setting gives the plain result
+            sable.sable_plan_set_variant(p, 0, v)
+            sable.sable_spmv(p, xd, y1)
+            torch.cuda.synchronize()
+            assert torch.equal(y1.view(torch.int32), y2.view(torch.int32)), v
+
+
 def test_spmm_autotune_kept_per_width():
     """The SpMM variant tuned for one n stays in use for that n after tuning another n, and
     an explicit variant applies to every n."""
