@@ -1,5 +1,6 @@
 // Executor: tile schedule, fused SpMV / SpMM launches, plain CSR baseline, bf16 split.
 #include <algorithm>
+#include <cmath>
 
 #include "exec.h"
 #include "spmm_panel.h"
@@ -538,7 +539,8 @@ __global__ __launch_bounds__(256) void k_spmm_fused_valu(PlanView P, const float
 
 }  // namespace
 
-static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s);
+static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s,
+                        bool coarse);
 
 static void build_heads(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s);
 
@@ -569,7 +571,7 @@ void build_schedule(sable_plan_s& P, Schedule& S, int RT, bool with_formats, hip
     if (split) to_dev(S.row0, r0, s);  // uniform tiling already balanced: keep it implicit
   }
   build_tiles(P, S, RT, with_formats, col_order, s);
-  build_order(P, S, with_formats, s);
+  build_order(P, S, with_formats, s, col_order);
   if (balance) build_heads(P, S, with_formats, s);
 }
 
@@ -621,7 +623,11 @@ static void build_heads(const sable_plan_s& P, Schedule& S, bool with_formats, h
   HIPC(hipStreamSynchronize(s));
 }
 
-static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s) {
+// coarse: costs are compared in half-octave classes, so tiles of about the same cost keep their
+// row order (SpMM: neighbouring tiles read many of the same X rows, which then meet in L2);
+// tiles much heavier than the rest still go first.
+static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, hipStream_t s,
+                        bool coarse) {
   const int nt = S.ntiles;
   if (nt < 2) return;
   DBuf<i64> cost(nt);
@@ -634,6 +640,8 @@ static void build_order(const sable_plan_s& P, Schedule& S, bool with_formats, h
   LAUNCH_CHECK();
   std::vector<i64> hc;
   to_host(hc, cost.p, nt, s);
+  if (coarse)
+    for (auto& c : hc) c = (i64)std::floor(2.0 * std::log2(1.0 + (double)c));
   // slot i of XCD run x holds tile xcd_tile(8*i + x); sort each run's tiles by cost
   const int per = (nt + 7) >> 3;
   std::vector<int32_t> ord(nt);
