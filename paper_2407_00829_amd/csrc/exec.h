@@ -348,18 +348,30 @@ __device__ __forceinline__ void stream_body(const PlanView& P, StreamTile<RPT, T
       }
     }
   }
-  // 2. blocks
+  // 2. blocks; the next block's descriptor (list entry -> rectangle and value offset) is
+  // loaded while the current block computes, so a block waits only for its values
+  int4 bd = make_int4(0, 0, 0, 0);
+  i64 bvp = 0;
+  if (blo < bhi) {
+    const int b = P.tile_blk[blo];
+    bd = *reinterpret_cast<const int4*>(P.blk + 4 * b);
+    bvp = P.blk_val_ptr[b];
+  }
   for (int qb = blo; qb < bhi; ++qb) {
-    const int b = P.tile_blk[qb];
-    const int br0 = P.blk[4 * b], br1 = P.blk[4 * b + 1];
-    const int c0 = P.blk[4 * b + 2], c1 = P.blk[4 * b + 3];
+    const int br0 = bd.x, br1 = bd.y, c0 = bd.z, c1 = bd.w;
+    const i64 vp = bvp;
+    if (qb + 1 < bhi) {
+      const int b = P.tile_blk[qb + 1];
+      bd = *reinterpret_cast<const int4*>(P.blk + 4 * b);
+      bvp = P.blk_val_ptr[b];
+    }
     const int h = br1 - br0, w = c1 - c0;
     const int lo = max(br0, r0), hi = min(br1, rend);
     const int nrb = hi - lo;
     if (nrb <= 0) continue;
     const int S = nrb >= kSpmvThreads ? 1 : kSpmvThreads / nrb;
     const int cw = (w + S - 1) / S;
-    const T* vb = Vals<T>::vbr(P) + P.blk_val_ptr[b];
+    const T* vb = Vals<T>::vbr(P) + vp;
     __syncthreads();
     for (int i = t; i < nrb * S; i += kSpmvThreads) {
       const int rl = i % nrb, sl = i / nrb;
