@@ -8,6 +8,8 @@ fastest class on average; the network alone must stay within one point of always
 best single class (stored with the weights, chosen on the training labels; on these seeds the
 stored labels give 2.5% against 3.9%, and the mean over 32 re-timed matrices carries about a
 point of timing noise), and the shipped choice must beat the paper's default list."""
+import time
+
 import numpy as np
 import pytest
 
@@ -34,15 +36,25 @@ def test_learned_plan_regret_and_gain():
     assert 0 <= cc < planner.NCLASS
     P = torch.from_numpy(params).cuda()
     r_net, r_ship, r_const, g_def, g_plain, fb_count = [], [], [], [], [], 0
+    t_auto, t_exh = [], []
     for seed in SEEDS:
         _, A, x = planner.make_matrix(seed)
         rec = planner.label_matrix(A, x, reps=REPS)
         ip, ix, vv = sable.device_csr(A)
         xd = torch.from_numpy(x).cuda()
         y = torch.empty(A.nrows, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         p, c, conf, fb = sable.sable_plan_auto(A.nrows, A.ncols, ip, ix, vv, P, mean, std, 0.0, xd, y)
+        t_auto.append(time.perf_counter() - t0)
         p.destroy()
         assert not fb and 0 <= c < planner.NCLASS and 0.0 < conf <= 1.0
+        if len(t_exh) < 8:  # planning time of the exhaustive search itself (forced fallback)
+            t0 = time.perf_counter()
+            q, _, _, fq = sable.sable_plan_auto(A.nrows, A.ncols, ip, ix, vv, P, mean, std, 1.01, xd, y)
+            t_exh.append(time.perf_counter() - t0)
+            q.destroy()
+            assert fq
         t = np.array(rec["times"])
         best = int(np.argmin(t))
         shipped = best if conf < tau else c  # below tau the exhaustive search decides
@@ -58,6 +70,10 @@ def test_learned_plan_regret_and_gain():
     print(f"  mean regret: shipped {np.mean(r_ship):.4f} (fallback {fb_count}/{len(r_net)}), "
           f"network {np.mean(r_net):.4f}, best single class {np.mean(r_const):.4f}; "
           f"geomean gain over the default list {geo(g_def):.3f}, over plain CSR {geo(g_plain):.3f}")
+    ta, te = np.median(t_auto[:len(t_exh)]), np.median(t_exh)
+    print(f"  planning time (median of {len(t_exh)}): network {ta * 1e3:.0f} ms, exhaustive search "
+          f"{te * 1e3:.0f} ms ({te / ta:.1f}x)")
+    assert ta < te
     assert np.mean(r_ship) <= 0.05
     assert np.mean(r_net) <= np.mean(r_const) + 0.01
     assert geo(g_def) >= 1.0
