@@ -11,10 +11,14 @@ histogram, row-length statistics). All numerical work runs in libsable:
 This module only generates matrices, stores labels (append-only JSONL, resumable), loops
 over training batches and computes the summary statistics.
 
-Usage (GPU):
-  python -m paper_2407_00829_amd.planner label --out labels.jsonl --seeds 0:800
-  python -m paper_2407_00829_amd.planner train --labels labels.jsonl --train 0:600 --out w.npz
-  python -m paper_2407_00829_amd.planner eval --labels labels.jsonl --test 600:800 --weights w.npz
+Usage (GPU; the shipped weights were made this way, with training seeds labelled from 0 up
+for as long as the time allowed and the held-out seeds 100000..100199):
+  python -m paper_2407_00829_amd.planner label --out labels.jsonl --seeds 100000:100200
+  python -m paper_2407_00829_amd.planner label --out labels.jsonl --seeds 0:1000 --max-seconds 1080
+  python -m paper_2407_00829_amd.planner train --labels labels.jsonl --train 0:1000 --out w.npz \
+      --epochs 500 --tol 0.02 --target 0.03
+  python -m paper_2407_00829_amd.planner eval --labels labels.jsonl --test 100000:100200 \
+      --train 0:1000 --weights w.npz
 """
 from __future__ import annotations
 
